@@ -1,0 +1,156 @@
+/*
+ * tsds.h -- C ABI of the MI355X (gfx950) time-series downsampling library
+ * (libtsds.so).
+ *
+ * The library computes the data-parallel hot path of the downsamplers in
+ * "tsdownsample: high-performance time series downsampling for scalable
+ * visualization" (arXiv 2307.05389): the per-bin argmin/argmax scan behind
+ * MinMax, M4 and the MinMax preselection of MinMaxLTTB (Sec. 2.1, Listing 1;
+ * Sec. 2.2), and the bucketed triangle-area argmax of LTTB (Sec. 4, LTTB and
+ * MinMaxLTTB rows of Table 1).  The user-facing operation the paper defines is
+ *     downsample([x], y, n_out) -> indices                        (Sec. 2.3)
+ * x optional (absent = equally sampled without gaps), y mandatory, n_out the
+ * number of output points, fewer returned when x has gaps (empty bins).
+ *
+ * Conventions shared by every entry point
+ *   - All data pointers (x, y, outputs, workspace) are DEVICE pointers
+ *     (hipMalloc'ed or equivalent) unless the comment says "host".
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Every call only enqueues work on that stream and returns; results are
+ *     valid once the stream has reached that point.  Nothing is allocated
+ *     on the device by the compute calls; the caller owns every buffer, and
+ *     the library keeps no pointer after a call returns.
+ *   - Indices are int64, into the caller's series, strictly increasing.
+ *   - x must be sorted non-decreasing and finite; y must hold no NaN.
+ *     These preconditions are not checked (checking would cost a pass over
+ *     the data); violating them gives unspecified but in-bounds indices.
+ *   - Every element pointer must be aligned to its element size.
+ *   - Return value: TS_OK (0) or a negative TS_ERR_* code.  All argument
+ *     checks happen before anything is enqueued, so an error leaves every
+ *     output untouched.  ts_last_error() gives a thread-local message.
+ *
+ * Workspace: each compute call takes a scratch buffer `ws` of at least
+ * ts_workspace_bytes(...) bytes (device memory, any content, 256-byte
+ * aligned).  Calls that overlap in time must not share a workspace.
+ */
+#ifndef TSDS_H
+#define TSDS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Element types (the dtypes the paper's argminmax supports, Sec. 2.1). */
+enum {
+  TS_NONE = -1, /* x absent */
+  TS_I8 = 0, TS_I16 = 1, TS_I32 = 2, TS_I64 = 3,
+  TS_U8 = 4, TS_U16 = 5, TS_U32 = 6, TS_U64 = 7,
+  TS_F16 = 8, TS_F32 = 9, TS_F64 = 10
+};
+
+/* Status codes. */
+enum {
+  TS_OK = 0,
+  TS_ERR_ARG = -1,        /* bad size, n_out or ratio */
+  TS_ERR_DTYPE = -2,      /* unsupported dtype for that argument */
+  TS_ERR_NULL = -3,       /* required pointer is NULL, or x/x_dtype mismatch */
+  TS_ERR_WORKSPACE = -4,  /* ws_bytes smaller than required, or ws misaligned */
+  TS_ERR_HIP = -5,        /* a HIP runtime call or kernel launch failed */
+  TS_ERR_ALIGN = -6       /* an element pointer is not aligned to its size */
+};
+
+/* Algorithms. */
+enum { TS_MINMAX = 0, TS_M4 = 1, TS_LTTB = 2, TS_MINMAXLTTB = 3 };
+
+/* One series.  y: n elements of y_dtype (any of the 11 types).
+ * x: NULL (x_dtype = TS_NONE) or n sorted elements of x_dtype in
+ * {TS_I32, TS_I64, TS_U32, TS_U64, TS_F32, TS_F64}. */
+typedef struct {
+  const void *x;
+  int32_t x_dtype;
+  const void *y;
+  int32_t y_dtype;
+  int64_t n;
+} ts_series;
+
+/* Library version (major*10000 + minor*100 + patch). */
+int ts_version(void);
+
+/* Message describing the last error returned on this host thread. */
+const char *ts_last_error(void);
+
+/* Bytes of workspace `algo` needs for this series and n_out (minmax_ratio is
+ * read for TS_MINMAXLTTB only).  Returns 0 if the arguments are invalid;
+ * a valid call may also need 0 bytes only if n <= n_out. */
+size_t ts_workspace_bytes(int algo, const ts_series *s, int64_t n_out, int64_t minmax_ratio);
+
+/* MinMax (Sec. 2.1, Sec. 2.2): n_out/2 bins; each non-empty bin keeps the
+ * first index of its minimum and the first index of its maximum.
+ * Bins: without x, bin b = [ceil(b(n-1)/nb), ceil((b+1)(n-1)/nb)) with the
+ * last bin ending at n (equal index ranges, identical to x = 0..n-1); with
+ * x, nb equal-width bins over [x[0], x[n-1]] located by search-sorted, the
+ * last bin closed on both sides.  n_out must be even and >= 2.
+ * n <= n_out returns 0..n-1.  out_idx: device int64[n_out] (written up to
+ * *out_count); out_count: device int64[1]. */
+int ts_minmax(const ts_series *s, int64_t n_out, int64_t *out_idx, int64_t *out_count,
+              void *ws, size_t ws_bytes, void *stream);
+
+/* M4 (Jugel et al., cited in Sec. 1): n_out/4 bins, same bins as MinMax;
+ * each non-empty bin keeps its first index, argmin, argmax and last index,
+ * de-duplicated.  n_out must be a multiple of 4 and >= 4. */
+int ts_m4(const ts_series *s, int64_t n_out, int64_t *out_idx, int64_t *out_count,
+          void *ws, size_t ws_bytes, void *stream);
+
+/* LTTB (Steinarsson, cited in Sec. 1; Sec. 4): first and last point kept;
+ * the n-2 interior points split into n_out-2 buckets by count
+ * (bucket k = [1+floor(k(n-2)/(n_out-2)), 1+floor((k+1)(n-2)/(n_out-2))));
+ * walking the buckets in order, each keeps the first point of largest
+ * triangle area with the previous pick and the mean (x, y) of the next
+ * bucket (the last bucket uses the last point).  Coordinates are x (or the
+ * index) and y, widened to double; means use exact integer sums for integer
+ * coordinates; the area is |(XA-Cx)(Yb-YA) - (XA-Xb)(Cy-YA)| in double with
+ * no fused multiply-add.  n_out >= 3; *out_count = min(n, n_out). */
+int ts_lttb(const ts_series *s, int64_t n_out, int64_t *out_idx, int64_t *out_count,
+            void *ws, size_t ws_bytes, void *stream);
+
+/* MinMaxLTTB (Van Der Donckt et al., cited in Sec. 1; Sec. 4): MinMax with
+ * n_out*minmax_ratio outputs over the interior points 1..n-2 (x-range bins
+ * over the interior when x is given) plus the first and last point form the
+ * candidates; LTTB with n_out outputs runs on the candidates with their
+ * original coordinates.  minmax_ratio >= 1, n_out*minmax_ratio even. */
+int ts_minmaxlttb(const ts_series *s, int64_t n_out, int64_t minmax_ratio, int64_t *out_idx,
+                  int64_t *out_count, void *ws, size_t ws_bytes, void *stream);
+
+/* ---- Single steps of the path, exposed so each can be checked alone ---- */
+
+/* Bin starts edges[0..nb] (edges[nb] = n) as used by ts_minmax / ts_m4 for
+ * nb bins (search-sorted binning, Sec. 2.2).  edges: device int64[nb+1]. */
+int ts_bin_edges(const ts_series *s, int64_t nb, int64_t *edges, void *stream);
+
+/* Per-bin argmin/argmax over the bins given by edges[0..nb] (device int64,
+ * non-decreasing, edges[0] >= 0, edges[nb] <= n): imin[b], imax[b] (device
+ * int64[nb]) receive the first index of the bin's minimum / maximum, or -1
+ * for an empty bin (Sec. 2.1, Listing 1).  ws: ts_argminmax_workspace_bytes. */
+size_t ts_argminmax_workspace_bytes(const ts_series *s, int64_t nb);
+int ts_bin_argminmax(const ts_series *s, const int64_t *edges, int64_t nb, int64_t *imin,
+                     int64_t *imax, void *ws, size_t ws_bytes, void *stream);
+
+/* LTTB centres for m points taken through `sel` (device int64[m] indices
+ * into the series, or NULL for all n points): cx[k], cy[k] (device
+ * double[n_out-2]) = mean x and y of bucket k+1, or the last point for the
+ * last bucket.  Requires m > n_out >= 3. */
+int ts_lttb_centres(const ts_series *s, const int64_t *sel, int64_t m, int64_t n_out,
+                    double *cx, double *cy, void *stream);
+
+/* Zoom window: [i0, i1) = the points with xa <= x <= xb, written to the
+ * device int64[2] `range` (integer x only). */
+int ts_window(const ts_series *s, int64_t xa, int64_t xb, int64_t *range, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TSDS_H */
