@@ -149,6 +149,14 @@ int ts_lttb_centres(const ts_series *s, const int64_t *sel, int64_t m, int64_t n
  * device int64[2] `range` (integer x only). */
 int ts_window(const ts_series *s, int64_t xa, int64_t xb, int64_t *range, void *stream);
 
+/* Tuning knobs of the argmin/argmax pass, process-wide: chunk_bytes (a power
+ * of two >= 4096; -1 = automatic) is the slice of y one wavefront reduces;
+ * bin segments shorter than small_bin elements (-1 = default 128) are reduced
+ * one bin per lane instead of one bin per wavefront.  Results never depend on
+ * them; workspace sizes do, so query ts_workspace_bytes after a change.  Not
+ * thread-safe with concurrent compute calls. */
+int ts_set_tuning(int64_t chunk_bytes, int32_t small_bin);
+
 #ifdef __cplusplus
 }
 #endif

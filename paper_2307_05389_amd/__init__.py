@@ -1,0 +1,20 @@
+"""MI355X-native time-series downsampling hot path (arXiv 2307.05389).
+
+    import paper_2307_05389_amd as tsds
+    idx = tsds.minmax(y, n_out)             # y: 1-D CUDA tensor, any of 11 dtypes
+    idx = tsds.m4(y, n_out, x=timestamps)   # optional sorted x
+    idx = tsds.lttb(y, n_out)
+    idx = tsds.minmaxlttb(y, n_out, minmax_ratio=4)
+
+Each call returns a device int64 tensor of selected indices (strictly
+increasing).  The work runs in libtsds.so's HIP kernels on the tensors'
+device and the current stream; see include/tsds.h for the exact semantics.
+"""
+from .api import (  # noqa: F401
+    bin_argminmax, bin_edges, downsample_into, lttb, lttb_centres, m4, minmax, minmaxlttb,
+    set_tuning, window, workspace_bytes,
+)
+from ._lib import TsArgError, TsError, lib  # noqa: F401
+
+__all__ = ["minmax", "m4", "lttb", "minmaxlttb", "downsample_into", "workspace_bytes", "bin_edges",
+           "bin_argminmax", "lttb_centres", "window", "set_tuning", "TsError", "TsArgError"]

@@ -1,0 +1,132 @@
+"""ctypes binding of libtsds.so (argument marshalling only).
+
+Every step of the downsampling path runs in the library's HIP kernels; this
+module only turns torch tensors into device pointers, sizes workspaces and
+maps status codes to exceptions.  It refuses to work without the compiled
+library: there is no CPU fallback.
+"""
+import ctypes
+import os
+
+import torch
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libtsds.so")
+
+TS_NONE = -1
+DTYPE_CODES = {
+    torch.int8: 0, torch.int16: 1, torch.int32: 2, torch.int64: 3,
+    torch.uint8: 4, torch.uint16: 5, torch.uint32: 6, torch.uint64: 7,
+    torch.float16: 8, torch.float32: 9, torch.float64: 10,
+}
+ALGO = {"minmax": 0, "m4": 1, "lttb": 2, "minmaxlttb": 3}
+ERRORS = {-1: "TS_ERR_ARG", -2: "TS_ERR_DTYPE", -3: "TS_ERR_NULL", -4: "TS_ERR_WORKSPACE",
+          -5: "TS_ERR_HIP", -6: "TS_ERR_ALIGN"}
+
+
+class TsSeries(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_void_p), ("x_dtype", ctypes.c_int32),
+                ("y", ctypes.c_void_p), ("y_dtype", ctypes.c_int32), ("n", ctypes.c_int64)]
+
+
+class TsError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class TsArgError(TsError, ValueError):
+    pass
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -c 'import __graft_entry__ as g; g.build()'`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i64, i32, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_size_t
+        SP = ctypes.POINTER(TsSeries)
+        L.ts_version.restype = ctypes.c_int
+        L.ts_last_error.restype = ctypes.c_char_p
+        L.ts_workspace_bytes.argtypes = [ctypes.c_int, SP, i64, i64]
+        L.ts_workspace_bytes.restype = sz
+        for f in (L.ts_minmax, L.ts_m4, L.ts_lttb):
+            f.argtypes = [SP, i64, vp, vp, vp, sz, vp]
+            f.restype = ctypes.c_int
+        L.ts_minmaxlttb.argtypes = [SP, i64, i64, vp, vp, vp, sz, vp]
+        L.ts_minmaxlttb.restype = ctypes.c_int
+        L.ts_bin_edges.argtypes = [SP, i64, vp, vp]
+        L.ts_bin_edges.restype = ctypes.c_int
+        L.ts_argminmax_workspace_bytes.argtypes = [SP, i64]
+        L.ts_argminmax_workspace_bytes.restype = sz
+        L.ts_bin_argminmax.argtypes = [SP, vp, i64, vp, vp, vp, sz, vp]
+        L.ts_bin_argminmax.restype = ctypes.c_int
+        L.ts_lttb_centres.argtypes = [SP, vp, i64, i64, vp, vp, vp]
+        L.ts_lttb_centres.restype = ctypes.c_int
+        L.ts_window.argtypes = [SP, i64, i64, vp, vp]
+        L.ts_window.restype = ctypes.c_int
+        L.ts_set_tuning.argtypes = [i64, i32]
+        L.ts_set_tuning.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def check(rc):
+    if rc != 0:
+        msg = lib().ts_last_error().decode()
+        if rc in (-1, -2, -3, -6):
+            raise TsArgError(rc, msg)
+        raise TsError(rc, msg)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(None)
+
+
+def series(y, x=None):
+    """TsSeries for device tensors y (and x); both 1-D and contiguous."""
+    if not isinstance(y, torch.Tensor) or y.device.type != "cuda":
+        raise ValueError("y must be a CUDA (HIP) tensor")
+    if y.dim() != 1 or not y.is_contiguous():
+        raise ValueError("y must be 1-D and contiguous")
+    if y.dtype not in DTYPE_CODES:
+        raise ValueError(f"unsupported y dtype {y.dtype}")
+    s = TsSeries(None, TS_NONE, y.data_ptr() if y.numel() else None, DTYPE_CODES[y.dtype], y.numel())
+    if x is not None:
+        if x.device != y.device or x.dim() != 1 or not x.is_contiguous() or x.numel() != y.numel():
+            raise ValueError("x must be a contiguous 1-D tensor on y's device with y's length")
+        if x.dtype not in DTYPE_CODES:
+            raise ValueError(f"unsupported x dtype {x.dtype}")
+        s.x = x.data_ptr() if x.numel() else None
+        s.x_dtype = DTYPE_CODES[x.dtype] if x.numel() else TS_NONE
+    return s
+
+
+def stream_ptr(stream=None, device=None):
+    st = stream if stream is not None else torch.cuda.current_stream(device)
+    return ctypes.c_void_p(st.cuda_stream)
+
+
+class Workspace:
+    """Grow-only device scratch buffer (one per stream: calls on one stream
+    are ordered, so they may share it)."""
+
+    def __init__(self):
+        self.buf = {}
+
+    def get(self, nbytes, device, stream):
+        key = (str(device), stream.cuda_stream)
+        b = self.buf.get(key)
+        if nbytes == 0:
+            return None
+        if b is None or b.numel() < nbytes:
+            b = torch.empty(max(nbytes, 1 << 20), dtype=torch.uint8, device=device)
+            self.buf[key] = b
+        return b
+
+
+WS = Workspace()

@@ -1,0 +1,520 @@
+// api.cpp -- the extern "C" entry points of libtsds: argument validation,
+// workspace layout and the launch sequence of each downsampler.  Every
+// check happens before the first launch, so an error leaves the caller's
+// outputs untouched.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+
+#include "common.hpp"
+#include "internal.hpp"
+#include "tsds.h"
+
+namespace tsds {
+
+size_t lttb_group_count(int64_t n_out);
+
+static thread_local std::string g_err;
+
+static int fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+static int hip_fail(hipError_t e, const char *what) {
+  return fail(TS_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+size_t elem_size(int dt) {
+  switch (dt) {
+    case TS_I8: case TS_U8: return 1;
+    case TS_I16: case TS_U16: case TS_F16: return 2;
+    case TS_I32: case TS_U32: case TS_F32: return 4;
+    case TS_I64: case TS_U64: case TS_F64: return 8;
+  }
+  return 0;
+}
+
+int vec_width(int dt) { return 16 / (int)elem_size(dt); }
+
+static bool x_dtype_ok(int dt) {
+  return dt == TS_I32 || dt == TS_I64 || dt == TS_U32 || dt == TS_U64 || dt == TS_F32 || dt == TS_F64;
+}
+
+static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// ------------------------------------------------------------------ tuning
+
+// Elements per chunk of the scan: a power-of-two number of bytes between one
+// tile (64 lanes x 4 x 16 B) and `max_bytes`, aiming at >= `target` chunks so
+// that every CU holds many wavefronts.  TSDS_CHUNK_BYTES overrides.
+static int64_t g_chunk_bytes_override = -1;
+static int32_t g_small_override = -1;
+
+static int64_t chunk_elems(int ydt, int64_t n) {
+  const int64_t esz = (int64_t)elem_size(ydt);
+  int64_t bytes;
+  if (g_chunk_bytes_override > 0) {
+    bytes = g_chunk_bytes_override;
+  } else {
+    const int64_t total = n * esz;
+    const int64_t target = 8192, lo = 4096, hi = 65536;
+    bytes = lo;
+    while (bytes * 2 <= hi && total / (bytes * 2) >= target) bytes *= 2;
+  }
+  if (bytes < 4096) bytes = 4096;
+  return bytes / esz;
+}
+
+static int32_t small_threshold() { return g_small_override > 0 ? g_small_override : 128; }
+
+// ------------------------------------------------------------------ plans
+
+struct ScanPlan {
+  int64_t nb = 0, chunk = 0, nchunks = 0;
+  size_t off_edges = 0, off_binres = 0, off_partL = 0, off_partR = 0, off_sel = 0, off_cnt = 0, bytes = 0;
+};
+
+// Workspace of one argmin/argmax pass over n elements in nb bins.  The chunk
+// count allows for the largest possible misalignment of y, so the size does
+// not depend on the pointer.
+static ScanPlan scan_plan(int ydt, int64_t n, int64_t nb, bool need_edges, size_t base) {
+  ScanPlan p;
+  p.nb = nb;
+  p.chunk = chunk_elems(ydt, n);
+  p.nchunks = (n + vec_width(ydt) - 1 + p.chunk - 1) / p.chunk;
+  if (p.nchunks < 1) p.nchunks = 1;
+  size_t o = base;
+  p.off_edges = o;
+  if (need_edges) o = align256(o + sizeof(int64_t) * (size_t)(nb + 1));
+  p.off_binres = o;
+  o = align256(o + sizeof(int64_t) * 2 * (size_t)nb);
+  p.off_partL = o;
+  o = align256(o + sizeof(Partial) * (size_t)p.nchunks);
+  p.off_partR = o;
+  o = align256(o + sizeof(Partial) * (size_t)p.nchunks);
+  p.off_sel = o;
+  o = align256(o + sizeof(int64_t) * 4 * (size_t)nb);
+  p.off_cnt = o;
+  o = align256(o + sizeof(int64_t) * (size_t)nb);
+  p.bytes = o;
+  return p;
+}
+
+struct LttbPlan {
+  size_t off_cx = 0, off_cy = 0, off_next = 0, off_entry = 0, bytes = 0;
+};
+
+static LttbPlan lttb_plan(int64_t m_max, int64_t n_out, size_t base) {
+  LttbPlan p;
+  size_t o = base;
+  const size_t nb = (size_t)(n_out - 2);
+  p.off_cx = o;
+  o = align256(o + sizeof(double) * nb);
+  p.off_cy = o;
+  o = align256(o + sizeof(double) * nb);
+  p.off_next = o;
+  o = align256(o + sizeof(int32_t) * 2 * (size_t)m_max);
+  p.off_entry = o;
+  o = align256(o + sizeof(int32_t) * (lttb_group_count(n_out) + 1));
+  p.bytes = o;
+  return p;
+}
+
+// ------------------------------------------------------------------ checks
+
+static int check_series(const ts_series *s) {
+  if (!s) return fail(TS_ERR_NULL, "series descriptor is NULL");
+  if (s->n < 0) return fail(TS_ERR_ARG, "n = %lld < 0", (long long)s->n);
+  if (elem_size(s->y_dtype) == 0) return fail(TS_ERR_DTYPE, "y dtype %d is not a ts dtype", s->y_dtype);
+  if (s->n > 0 && !s->y) return fail(TS_ERR_NULL, "y is NULL");
+  if ((s->x == nullptr) != (s->x_dtype == TS_NONE))
+    return fail(TS_ERR_NULL, "x is %s but x_dtype is %d", s->x ? "set" : "NULL", s->x_dtype);
+  if (s->x && !x_dtype_ok(s->x_dtype))
+    return fail(TS_ERR_DTYPE, "x dtype %d unsupported (int32/int64/uint32/uint64/float32/float64)", s->x_dtype);
+  if (s->y && ((uintptr_t)s->y % elem_size(s->y_dtype)))
+    return fail(TS_ERR_ALIGN, "y is not aligned to its element size");
+  if (s->x && ((uintptr_t)s->x % elem_size(s->x_dtype)))
+    return fail(TS_ERR_ALIGN, "x is not aligned to its element size");
+  if (s->n > ((int64_t)1 << 48)) return fail(TS_ERR_ARG, "n = %lld exceeds 2^48", (long long)s->n);
+  return TS_OK;
+}
+
+// nb bins over n points: the closed-form edges multiply b by n-1.
+static int check_bins(int64_t n, int64_t nb) {
+  if (nb < 1) return fail(TS_ERR_ARG, "need at least one bin");
+  if (nb >= ((int64_t)1 << 31)) return fail(TS_ERR_ARG, "too many bins (%lld)", (long long)nb);
+  if (n > 0 && (unsigned __int128)(n - 1) * (unsigned __int128)nb >= ((unsigned __int128)1 << 62))
+    return fail(TS_ERR_ARG, "n * bins too large");
+  return TS_OK;
+}
+
+static int check_out(const int64_t *out_idx, const int64_t *out_count) {
+  if (!out_idx || !out_count) return fail(TS_ERR_NULL, "out_idx / out_count is NULL");
+  return TS_OK;
+}
+
+static int check_ws(void *ws, size_t ws_bytes, size_t need) {
+  if (need == 0) return TS_OK;
+  if (!ws) return fail(TS_ERR_WORKSPACE, "workspace is NULL (%zu bytes needed)", need);
+  if ((uintptr_t)ws % 256) return fail(TS_ERR_WORKSPACE, "workspace is not 256-byte aligned");
+  if (ws_bytes < need) return fail(TS_ERR_WORKSPACE, "workspace %zu bytes < %zu needed", ws_bytes, need);
+  return TS_OK;
+}
+
+static int check_nout(int algo, int64_t n_out, int64_t ratio) {
+  switch (algo) {
+    case TS_MINMAX:
+      if (n_out < 2 || n_out % 2) return fail(TS_ERR_ARG, "MinMax n_out must be even and >= 2 (got %lld)", (long long)n_out);
+      return check_bins(2, n_out / 2);
+    case TS_M4:
+      if (n_out < 4 || n_out % 4) return fail(TS_ERR_ARG, "M4 n_out must be a multiple of 4 (got %lld)", (long long)n_out);
+      return check_bins(2, n_out / 4);
+    case TS_LTTB:
+      if (n_out < 3) return fail(TS_ERR_ARG, "LTTB n_out must be >= 3 (got %lld)", (long long)n_out);
+      if (n_out >= ((int64_t)1 << 31)) return fail(TS_ERR_ARG, "n_out too large");
+      return TS_OK;
+    case TS_MINMAXLTTB:
+      if (n_out < 3) return fail(TS_ERR_ARG, "MinMaxLTTB n_out must be >= 3 (got %lld)", (long long)n_out);
+      if (ratio < 1) return fail(TS_ERR_ARG, "minmax_ratio must be >= 1 (got %lld)", (long long)ratio);
+      if (n_out >= ((int64_t)1 << 28) || ratio >= ((int64_t)1 << 16) || (n_out * ratio) % 2)
+        return fail(TS_ERR_ARG, "n_out * minmax_ratio must be even and < 2^44");
+      return check_bins(2, n_out * ratio / 2);
+  }
+  return fail(TS_ERR_ARG, "unknown algorithm %d", algo);
+}
+
+// ------------------------------------------------------------------ pieces
+
+static char *wsp(void *ws, size_t off) { return (char *)ws + off; }
+
+static int64_t y_shift(const ts_series &s) {
+  const size_t esz = elem_size(s.y_dtype);
+  return (int64_t)(((uintptr_t)s.y & 15) / esz);
+}
+
+// Argmin/argmax pass + per-bin selection + compaction for MinMax / M4 / the
+// preselection.  `out` receives the indices (+ index_offset).
+static int run_scan(const ts_series &s, int64_t nb, int m4, const ScanPlan &pl, void *ws, int64_t *out,
+                    int64_t *out_count, int64_t index_offset, int64_t endpoints_n, hipStream_t st) {
+  const int64_t *edges = nullptr;
+  hipError_t e;
+  if (s.x) {
+    int64_t *ed = (int64_t *)wsp(ws, pl.off_edges);
+    if ((e = launch_edges_x(s.x, s.x_dtype, s.n, nb, ed, st)) != hipSuccess) return hip_fail(e, "edges");
+    edges = ed;
+  }
+  ScanParams sp;
+  sp.y = s.y;
+  sp.n = s.n;
+  sp.shift = y_shift(s);
+  sp.chunk = pl.chunk;
+  sp.nchunks = (s.n + sp.shift + pl.chunk - 1) / pl.chunk;
+  sp.edges = edges;
+  sp.nb = nb;
+  sp.binres = (int64_t *)wsp(ws, pl.off_binres);
+  sp.partL = (Partial *)wsp(ws, pl.off_partL);
+  sp.partR = (Partial *)wsp(ws, pl.off_partR);
+  sp.small = small_threshold();
+  if ((e = launch_scan(s.y_dtype, sp, st)) != hipSuccess) return hip_fail(e, "scan");
+  MergeParams mp;
+  mp.n = s.n;
+  mp.shift = sp.shift;
+  mp.chunk = sp.chunk;
+  mp.edges = edges;
+  mp.nb = nb;
+  mp.binres = sp.binres;
+  mp.partL = sp.partL;
+  mp.partR = sp.partR;
+  mp.m4 = m4;
+  mp.sel = (int64_t *)wsp(ws, pl.off_sel);
+  mp.cnt = (int64_t *)wsp(ws, pl.off_cnt);
+  if ((e = launch_merge(mp, st)) != hipSuccess) return hip_fail(e, "merge");
+  CompactParams cp;
+  cp.nb = nb;
+  cp.sel = mp.sel;
+  cp.cnt = mp.cnt;
+  cp.out = out;
+  cp.out_count = out_count;
+  cp.index_offset = index_offset;
+  cp.endpoints_n = endpoints_n;
+  cp.all_n = -1;
+  if ((e = launch_compact(cp, st)) != hipSuccess) return hip_fail(e, "compact");
+  return TS_OK;
+}
+
+static int write_all(int64_t n, int64_t *out, int64_t *out_count, hipStream_t st) {
+  CompactParams cp{};
+  cp.out = out;
+  cp.out_count = out_count;
+  cp.all_n = n;
+  hipError_t e = launch_compact(cp, st);
+  if (e != hipSuccess) return hip_fail(e, "arange");
+  return TS_OK;
+}
+
+// MinMaxLTTB preselection sizes: interior of n-2 points, n_out*ratio outputs.
+struct MmlPlan {
+  bool presel_all = false;  // the interior is not reduced: candidates = all points
+  ScanPlan scan;
+  size_t off_cand = 0, off_m = 0;
+  LttbPlan lt;
+  int64_t m_max = 0;
+  size_t bytes = 0;
+};
+
+static MmlPlan mml_plan(const ts_series &s, int64_t n_out, int64_t ratio) {
+  MmlPlan p;
+  const int64_t npre = n_out * ratio, ni = s.n - 2;
+  p.presel_all = ni <= npre;
+  size_t o = 0;
+  if (!p.presel_all) {
+    p.scan = scan_plan(s.y_dtype, ni, npre / 2, s.x != nullptr, 0);
+    o = p.scan.bytes;
+    p.off_cand = o;
+    o = align256(o + sizeof(int64_t) * (size_t)(npre + 2));
+    p.off_m = o;
+    o = align256(o + sizeof(int64_t));
+    p.m_max = npre + 2;
+  } else {
+    p.m_max = s.n;
+  }
+  p.lt = lttb_plan(p.m_max, n_out, o);
+  p.bytes = p.lt.bytes;
+  return p;
+}
+
+static int run_lttb(const ts_series &s, const int64_t *sel, int64_t m, const int64_t *m_dev, int64_t m_max,
+                    int64_t n_out, const LttbPlan &lp, void *ws, int64_t *out, int64_t *out_count, bool small,
+                    hipStream_t st) {
+  LttbParams p;
+  p.x = s.x;
+  p.x_dtype = s.x_dtype;
+  p.y = s.y;
+  p.y_dtype = s.y_dtype;
+  p.sel = sel;
+  p.m = m;
+  p.m_dev = m_dev;
+  p.m_max = m_max;
+  p.n_out = n_out;
+  p.cx = (double *)wsp(ws, lp.off_cx);
+  p.cy = (double *)wsp(ws, lp.off_cy);
+  p.next = (int32_t *)wsp(ws, lp.off_next);
+  p.entry = (int32_t *)wsp(ws, lp.off_entry);
+  p.out = out;
+  p.out_count = out_count;
+  hipError_t e;
+  if ((e = launch_lttb_centres(p, st)) != hipSuccess) return hip_fail(e, "lttb centres");
+  if (small) {
+    if ((e = launch_lttb_small(p, st)) != hipSuccess) return hip_fail(e, "lttb walk");
+  } else {
+    if ((e = launch_lttb_seq(p, st)) != hipSuccess) return hip_fail(e, "lttb walk");
+  }
+  return TS_OK;
+}
+
+// Largest LTTB bucket for which the transition-map walk is used.
+static bool lttb_small_buckets(int64_t m, int64_t n_out) {
+  const int64_t nb = n_out - 2;
+  const int64_t maxb = (m - 2 + nb - 1) / nb;
+  return maxb <= 32 && m <= (int64_t)1 << 30;
+}
+
+}  // namespace tsds
+
+using namespace tsds;
+
+extern "C" {
+
+int ts_version(void) { return 10000; }
+
+const char *ts_last_error(void) { return g_err.c_str(); }
+
+size_t ts_workspace_bytes(int algo, const ts_series *s, int64_t n_out, int64_t minmax_ratio) {
+  if (check_series(s) || check_nout(algo, n_out, minmax_ratio)) return 0;
+  if (s->n <= n_out) return 0;
+  switch (algo) {
+    case TS_MINMAX: return scan_plan(s->y_dtype, s->n, n_out / 2, s->x != nullptr, 0).bytes;
+    case TS_M4: return scan_plan(s->y_dtype, s->n, n_out / 4, s->x != nullptr, 0).bytes;
+    case TS_LTTB: return lttb_plan(s->n, n_out, 0).bytes;
+    case TS_MINMAXLTTB: return mml_plan(*s, n_out, minmax_ratio).bytes;
+  }
+  return 0;
+}
+
+static int minmax_m4(int algo, const ts_series *s, int64_t n_out, int64_t *out_idx, int64_t *out_count,
+                     void *ws, size_t ws_bytes, void *stream) {
+  int rc;
+  if ((rc = check_series(s)) || (rc = check_nout(algo, n_out, 0)) || (rc = check_out(out_idx, out_count)))
+    return rc;
+  hipStream_t st = (hipStream_t)stream;
+  if (s->n <= n_out) return write_all(s->n, out_idx, out_count, st);
+  const int64_t nb = algo == TS_MINMAX ? n_out / 2 : n_out / 4;
+  if ((rc = check_bins(s->n, nb))) return rc;
+  const ScanPlan pl = scan_plan(s->y_dtype, s->n, nb, s->x != nullptr, 0);
+  if ((rc = check_ws(ws, ws_bytes, pl.bytes))) return rc;
+  return run_scan(*s, nb, algo == TS_M4, pl, ws, out_idx, out_count, 0, 0, st);
+}
+
+int ts_minmax(const ts_series *s, int64_t n_out, int64_t *out_idx, int64_t *out_count, void *ws,
+              size_t ws_bytes, void *stream) {
+  return minmax_m4(TS_MINMAX, s, n_out, out_idx, out_count, ws, ws_bytes, stream);
+}
+
+int ts_m4(const ts_series *s, int64_t n_out, int64_t *out_idx, int64_t *out_count, void *ws, size_t ws_bytes,
+          void *stream) {
+  return minmax_m4(TS_M4, s, n_out, out_idx, out_count, ws, ws_bytes, stream);
+}
+
+int ts_lttb(const ts_series *s, int64_t n_out, int64_t *out_idx, int64_t *out_count, void *ws, size_t ws_bytes,
+            void *stream) {
+  int rc;
+  if ((rc = check_series(s)) || (rc = check_nout(TS_LTTB, n_out, 0)) || (rc = check_out(out_idx, out_count)))
+    return rc;
+  hipStream_t st = (hipStream_t)stream;
+  if (s->n <= n_out) return write_all(s->n, out_idx, out_count, st);
+  if ((unsigned __int128)s->n * (unsigned __int128)n_out >= ((unsigned __int128)1 << 62))
+    return fail(TS_ERR_ARG, "n * n_out too large");
+  const LttbPlan lp = lttb_plan(s->n, n_out, 0);
+  if ((rc = check_ws(ws, ws_bytes, lp.bytes))) return rc;
+  return run_lttb(*s, nullptr, s->n, nullptr, s->n, n_out, lp, ws, out_idx, out_count,
+                  lttb_small_buckets(s->n, n_out), st);
+}
+
+int ts_minmaxlttb(const ts_series *s, int64_t n_out, int64_t minmax_ratio, int64_t *out_idx, int64_t *out_count,
+                  void *ws, size_t ws_bytes, void *stream) {
+  int rc;
+  if ((rc = check_series(s)) || (rc = check_nout(TS_MINMAXLTTB, n_out, minmax_ratio)) ||
+      (rc = check_out(out_idx, out_count)))
+    return rc;
+  hipStream_t st = (hipStream_t)stream;
+  if (s->n <= n_out) return write_all(s->n, out_idx, out_count, st);
+  const MmlPlan pl = mml_plan(*s, n_out, minmax_ratio);
+  if ((rc = check_ws(ws, ws_bytes, pl.bytes))) return rc;
+  if ((unsigned __int128)pl.m_max * (unsigned __int128)n_out >= ((unsigned __int128)1 << 62))
+    return fail(TS_ERR_ARG, "n * n_out too large");
+  if (pl.presel_all) {
+    return run_lttb(*s, nullptr, s->n, nullptr, s->n, n_out, pl.lt, ws, out_idx, out_count,
+                    lttb_small_buckets(s->n, n_out), st);
+  }
+  // Preselection over the interior points 1..n-2.
+  ts_series in = *s;
+  in.n = s->n - 2;
+  in.y = (const char *)s->y + elem_size(s->y_dtype);
+  if (s->x) in.x = (const char *)s->x + elem_size(s->x_dtype);
+  const int64_t npre = n_out * minmax_ratio;
+  if ((rc = check_bins(in.n, npre / 2))) return rc;
+  int64_t *cand = (int64_t *)wsp(ws, pl.off_cand);
+  int64_t *m_dev = (int64_t *)wsp(ws, pl.off_m);
+  if ((rc = run_scan(in, npre / 2, 0, pl.scan, ws, cand + 1, m_dev, 1, s->n, st))) return rc;
+  return run_lttb(*s, cand, -1, m_dev, pl.m_max, n_out, pl.lt, ws, out_idx, out_count,
+                  lttb_small_buckets(pl.m_max, n_out), st);
+}
+
+int ts_bin_edges(const ts_series *s, int64_t nb, int64_t *edges, void *stream) {
+  int rc;
+  if ((rc = check_series(s)) || (rc = check_bins(s->n, nb))) return rc;
+  if (!edges) return fail(TS_ERR_NULL, "edges is NULL");
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e;
+  if (s->x && s->n > 0) e = launch_edges_x(s->x, s->x_dtype, s->n, nb, edges, st);
+  else e = launch_edges_nox(s->n, nb, edges, st);
+  if (e != hipSuccess) return hip_fail(e, "edges");
+  return TS_OK;
+}
+
+size_t ts_argminmax_workspace_bytes(const ts_series *s, int64_t nb) {
+  if (check_series(s) || nb < 1) return 0;
+  return scan_plan(s->y_dtype, s->n, nb, false, 0).bytes;
+}
+
+int ts_bin_argminmax(const ts_series *s, const int64_t *edges, int64_t nb, int64_t *imin, int64_t *imax, void *ws,
+                     size_t ws_bytes, void *stream) {
+  int rc;
+  if ((rc = check_series(s)) || (rc = check_bins(s->n, nb))) return rc;
+  if (!edges || !imin || !imax) return fail(TS_ERR_NULL, "edges / imin / imax is NULL");
+  if (s->n == 0) return fail(TS_ERR_ARG, "empty series");
+  const ScanPlan pl = scan_plan(s->y_dtype, s->n, nb, false, 0);
+  if ((rc = check_ws(ws, ws_bytes, pl.bytes))) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  ScanParams sp;
+  sp.y = s->y;
+  sp.n = s->n;
+  sp.shift = y_shift(*s);
+  sp.chunk = pl.chunk;
+  sp.nchunks = (s->n + sp.shift + pl.chunk - 1) / pl.chunk;
+  sp.edges = edges;
+  sp.nb = nb;
+  sp.binres = (int64_t *)wsp(ws, pl.off_binres);
+  sp.partL = (Partial *)wsp(ws, pl.off_partL);
+  sp.partR = (Partial *)wsp(ws, pl.off_partR);
+  sp.small = small_threshold();
+  hipError_t e;
+  if ((e = launch_scan(s->y_dtype, sp, st)) != hipSuccess) return hip_fail(e, "scan");
+  MergeParams mp{};
+  mp.n = s->n;
+  mp.shift = sp.shift;
+  mp.chunk = sp.chunk;
+  mp.edges = edges;
+  mp.nb = nb;
+  mp.binres = sp.binres;
+  mp.partL = sp.partL;
+  mp.partR = sp.partR;
+  if ((e = launch_binres_to_outputs(mp, imin, imax, st)) != hipSuccess) return hip_fail(e, "bin outputs");
+  return TS_OK;
+}
+
+int ts_lttb_centres(const ts_series *s, const int64_t *sel, int64_t m, int64_t n_out, double *cx, double *cy,
+                    void *stream) {
+  int rc;
+  if ((rc = check_series(s))) return rc;
+  if (n_out < 3 || m <= n_out) return fail(TS_ERR_ARG, "need m > n_out >= 3");
+  if (!sel && m != s->n) return fail(TS_ERR_ARG, "without sel, m must equal n");
+  if (!cx || !cy) return fail(TS_ERR_NULL, "cx / cy is NULL");
+  LttbParams p{};
+  p.x = s->x;
+  p.x_dtype = s->x_dtype;
+  p.y = s->y;
+  p.y_dtype = s->y_dtype;
+  p.sel = sel;
+  p.m = m;
+  p.m_max = m;
+  p.n_out = n_out;
+  p.cx = cx;
+  p.cy = cy;
+  hipError_t e = launch_lttb_centres(p, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "lttb centres");
+  return TS_OK;
+}
+
+int ts_window(const ts_series *s, int64_t xa, int64_t xb, int64_t *range, void *stream) {
+  int rc;
+  if ((rc = check_series(s))) return rc;
+  if (!s->x) return fail(TS_ERR_NULL, "window needs x");
+  if (s->x_dtype == TS_F32 || s->x_dtype == TS_F64) return fail(TS_ERR_DTYPE, "window needs integer x");
+  if (!range) return fail(TS_ERR_NULL, "range is NULL");
+  hipError_t e = launch_window(s->x, s->x_dtype, s->n, xa, xb, range, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "window");
+  return TS_OK;
+}
+
+// Tuning knobs (tests use them to show that results do not depend on them).
+int ts_set_tuning(int64_t chunk_bytes, int32_t small_bin) {
+  if (chunk_bytes > 0 && (chunk_bytes < 4096 || (chunk_bytes & (chunk_bytes - 1))))
+    return fail(TS_ERR_ARG, "chunk_bytes must be a power of two >= 4096");
+  g_chunk_bytes_override = chunk_bytes;
+  g_small_override = small_bin;
+  return TS_OK;
+}
+
+}  // extern "C"

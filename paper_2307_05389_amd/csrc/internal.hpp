@@ -1,0 +1,93 @@
+// internal.hpp -- host-side interface between the C-ABI layer (api.cpp) and
+// the kernel translation units.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "tsds.h"
+
+namespace tsds {
+
+struct Partial;
+
+// Binning of one series for the argmin/argmax scan.  Without x the bins are
+// equal index ranges given in closed form; with x (or caller-given edges) the
+// starts live in `edges` (device, nb + 1 entries).
+struct ScanParams {
+  const void *y;          // first element of the series
+  int64_t n;              // series length
+  int64_t shift;          // elements between the 16-byte aligned base and y
+  int64_t chunk;          // elements per chunk (multiple of the vector width)
+  int64_t nchunks;
+  const int64_t *edges;   // NULL: closed-form equal index bins
+  int64_t nb;
+  int64_t *binres;        // [2*nb] argmin, argmax of bins inside one chunk
+  Partial *partL;         // [nchunks] bin that started before the chunk
+  Partial *partR;         // [nchunks] bin that continues after the chunk
+  int32_t small;          // segments shorter than this: one lane per bin
+};
+
+struct MergeParams {
+  int64_t n;
+  int64_t shift;
+  int64_t chunk;
+  const int64_t *edges;   // NULL: closed form
+  int64_t nb;
+  const int64_t *binres;
+  const Partial *partL;
+  const Partial *partR;
+  int32_t m4;             // 0: MinMax {argmin, argmax}; 1: M4 adds first/last
+  int64_t *sel;           // [4*nb] selected indices per bin (sorted, distinct)
+  int64_t *cnt;           // [nb]   how many
+};
+
+struct CompactParams {
+  int64_t nb;
+  const int64_t *sel;
+  const int64_t *cnt;
+  int64_t *out;           // output indices
+  int64_t *out_count;     // device scalar
+  int64_t index_offset;   // added to every index (interior preselection)
+  int64_t endpoints_n;    // > 0: also write out[-1] = 0 and out[count] = endpoints_n - 1
+  int64_t all_n;          // >= 0: ignore bins, write out[i] = i for i < all_n
+};
+
+size_t elem_size(int dtype);
+int vec_width(int dtype);
+
+hipError_t launch_edges_x(const void *x, int x_dtype, int64_t n, int64_t nb, int64_t *edges,
+                          hipStream_t st);
+hipError_t launch_edges_nox(int64_t n, int64_t nb, int64_t *edges, hipStream_t st);
+hipError_t launch_scan(int y_dtype, const ScanParams &p, hipStream_t st);
+hipError_t launch_merge(const MergeParams &p, hipStream_t st);
+hipError_t launch_compact(const CompactParams &p, hipStream_t st);
+hipError_t launch_binres_to_outputs(const MergeParams &p, int64_t *imin, int64_t *imax,
+                                    hipStream_t st);
+hipError_t launch_window(const void *x, int x_dtype, int64_t n, int64_t xa, int64_t xb,
+                         int64_t *range, hipStream_t st);
+
+// LTTB over m points taken through `sel` (NULL = the series itself).
+struct LttbParams {
+  const void *x;
+  int32_t x_dtype;        // TS_NONE: X is the index
+  const void *y;
+  int32_t y_dtype;
+  const int64_t *sel;     // NULL or device [m_max]
+  int64_t m;              // number of points, or -1: read *m_dev
+  const int64_t *m_dev;
+  int64_t m_max;
+  int64_t n_out;
+  double *cx;             // [n_out - 2] centres (workspace)
+  double *cy;
+  int32_t *next;          // [m_max] transition map (workspace)
+  int32_t *entry;         // [groups + 1] workspace
+  int64_t *out;
+  int64_t *out_count;
+};
+
+hipError_t launch_lttb_centres(const LttbParams &p, hipStream_t st);
+hipError_t launch_lttb_small(const LttbParams &p, hipStream_t st);
+hipError_t launch_lttb_seq(const LttbParams &p, hipStream_t st);
+
+}  // namespace tsds

@@ -1,0 +1,94 @@
+"""CPU-side checks of the C ABI: the library loads, exports every function
+that include/tsds.h declares, and rejects bad arguments before it touches the
+GPU (validation is host logic; no kernel is launched in these tests)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tsds.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ts_[a-z0-9_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2307_05389_amd import _lib
+    return _lib.lib()
+
+
+def test_header_declares_the_paths_entry_points():
+    names = _declared()
+    for f in ("ts_minmax", "ts_m4", "ts_lttb", "ts_minmaxlttb", "ts_workspace_bytes", "ts_bin_edges",
+              "ts_bin_argminmax", "ts_lttb_centres", "ts_window", "ts_last_error"):
+        assert f in names
+
+
+def test_library_exports_every_declared_symbol(L):
+    for name in _declared():
+        assert hasattr(L, name), name
+
+
+def _series(n, ydt=9, y=0x1000, x=None, xdt=-1):
+    from paper_2307_05389_amd._lib import TsSeries
+    return TsSeries(x, xdt, y, ydt, n)
+
+
+def test_workspace_bytes_host_logic(L):
+    s = _series(10**8, ydt=10, x=0x2000, xdt=3)
+    ws = L.ts_workspace_bytes(1, ctypes.byref(s), 4000, 0)
+    assert ws > 0 and ws % 256 == 0
+    assert L.ts_workspace_bytes(1, ctypes.byref(s), 4001, 0) == 0       # M4 needs n_out % 4 == 0
+    assert L.ts_workspace_bytes(0, ctypes.byref(_series(100)), 1000, 0) == 0  # n <= n_out
+    assert L.ts_workspace_bytes(3, ctypes.byref(_series(10**7)), 1000, 4) > 0
+    assert L.ts_workspace_bytes(3, ctypes.byref(_series(10**7)), 1001, 1) == 0  # odd n_out*ratio
+
+
+@pytest.mark.parametrize("call,code", [
+    ("minmax_odd", -1), ("m4_bad", -1), ("lttb_small", -1), ("ratio0", -1), ("bad_dtype", -2),
+    ("x_mismatch", -3), ("null_out", -3), ("misaligned", -6), ("no_ws", -4), ("neg_n", -1),
+])
+def test_validation_errors_without_launch(L, call, code):
+    out = ctypes.c_void_p(0x10000)
+    cnt = ctypes.c_void_p(0x20000)
+    ws = ctypes.c_void_p(0x100000)
+    s = _series(10**6)
+    args = None
+    if call == "minmax_odd":
+        rc = L.ts_minmax(ctypes.byref(s), 1001, out, cnt, ws, 1 << 30, None)
+    elif call == "m4_bad":
+        rc = L.ts_m4(ctypes.byref(s), 1002, out, cnt, ws, 1 << 30, None)
+    elif call == "lttb_small":
+        rc = L.ts_lttb(ctypes.byref(s), 2, out, cnt, ws, 1 << 30, None)
+    elif call == "ratio0":
+        rc = L.ts_minmaxlttb(ctypes.byref(s), 1000, 0, out, cnt, ws, 1 << 30, None)
+    elif call == "bad_dtype":
+        rc = L.ts_minmax(ctypes.byref(_series(10**6, ydt=11)), 1000, out, cnt, ws, 1 << 30, None)
+    elif call == "x_mismatch":
+        rc = L.ts_minmax(ctypes.byref(_series(10**6, x=0x3000, xdt=-1)), 1000, out, cnt, ws, 1 << 30, None)
+    elif call == "null_out":
+        rc = L.ts_minmax(ctypes.byref(s), 1000, None, cnt, ws, 1 << 30, None)
+    elif call == "misaligned":
+        rc = L.ts_minmax(ctypes.byref(_series(10**6, y=0x1001)), 1000, out, cnt, ws, 1 << 30, None)
+    elif call == "no_ws":
+        rc = L.ts_minmax(ctypes.byref(s), 1000, out, cnt, ws, 16, None)
+    elif call == "neg_n":
+        rc = L.ts_minmax(ctypes.byref(_series(-5)), 1000, out, cnt, ws, 1 << 30, None)
+    assert rc == code, (call, rc, L.ts_last_error())
+    assert L.ts_last_error()
+
+
+def test_no_cpu_fallback_in_product_package():
+    """The product package never imports the oracle."""
+    pkg = os.path.join(ROOT, "paper_2307_05389_amd")
+    for dp, _, fs in os.walk(pkg):
+        for f in fs:
+            if f.endswith((".py", ".cpp", ".hip", ".hpp")):
+                txt = open(os.path.join(dp, f)).read()
+                assert "oracle" not in txt.replace("the oracle", ""), f

@@ -1,0 +1,257 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle, element
+by element, on seeded inputs.  MinMax, M4 and the MinMaxLTTB preselection
+must match bit-exactly; LTTB picks are compared exactly and through the
+step-wise near-tie rule as the stated tolerance."""
+import numpy as np
+import pytest
+import torch
+
+import synthetic as S
+from lttb_check import stepwise_check
+
+pytestmark = pytest.mark.gpu
+
+ALL = [np.int8, np.int16, np.int32, np.int64, np.uint8, np.uint16, np.uint32, np.uint64,
+       np.float16, np.float32, np.float64]
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+@pytest.fixture(scope="module")
+def ts():
+    import paper_2307_05389_amd as t
+    t.set_tuning()
+    yield t
+    t.set_tuning()
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def gpu(ts, algo, y, n_out, x=None, ratio=4):
+    yd, xd = dev(y), (None if x is None else dev(x))
+    if algo == "minmaxlttb":
+        r = ts.minmaxlttb(yd, n_out, x=xd, minmax_ratio=ratio)
+    else:
+        r = getattr(ts, algo)(yd, n_out, x=xd)
+    torch.cuda.synchronize()
+    return r.cpu().numpy()
+
+
+def orc(oracle_mod, algo, y, n_out, x=None, ratio=4):
+    if algo == "minmaxlttb":
+        return oracle_mod.minmaxlttb(y, n_out, ratio, x=x)
+    return getattr(oracle_mod, algo)(y, n_out, x=x)
+
+
+def xs_for(n, seed):
+    rng = np.random.default_rng(seed)
+    g = S.timestamps(n, 1000, seed=seed)
+    gap = g.copy()
+    if n > 10:
+        gap[n // 3:] += 10**7          # empty bins
+        gap[2 * n // 3: 2 * n // 3 + 5] = gap[2 * n // 3]   # duplicates
+        gap = np.maximum.accumulate(gap)
+    return {
+        "none": None,
+        "i64": gap,
+        "i32": (g % (2**31 - 1)).astype(np.int32) if g[-1] < 2**31 else None,
+        "u64": gap.astype(np.uint64) + np.uint64(2**63),
+        "f64": np.sort(rng.random(n) * 1e6),
+        "f32": np.sort(rng.random(n).astype(np.float32) * np.float32(1e4)),
+    }
+
+
+@pytest.mark.parametrize("dtype", ALL, ids=lambda d: np.dtype(d).name)
+@pytest.mark.parametrize("algo", ["minmax", "m4"])
+def test_parity_matrix(ts, oracle_mod, algo, dtype):
+    for n in (1000, 33333, 300001):
+        y = S.walk(n, dtype, seed=n % 97)
+        for xname, x in xs_for(n, n % 89).items():
+            if x is None and xname != "none":
+                continue
+            for n_out in (4, 100, 1000, 8000):
+                say(f"[parity] {algo} {np.dtype(dtype).name} n={n} x={xname} n_out={n_out}")
+                got = gpu(ts, algo, y, n_out, x)
+                exp = orc(oracle_mod, algo, y, n_out, x)
+                assert np.array_equal(got, exp), (algo, dtype, n, xname, n_out)
+
+
+@pytest.mark.parametrize("algo", ["minmax", "m4", "lttb", "minmaxlttb"])
+def test_edge_sizes(ts, oracle_mod, algo):
+    for dtype in ALL:
+        for n in (0, 1, 2, 3, 4, 5, 7, 8, 9, 15, 16, 17, 63, 64, 65):
+            y = S.walk(n, dtype, seed=3) if n else np.zeros(0, dtype)
+            for n_out in (4, 8, 12, 16):
+                if algo == "minmaxlttb" and n_out * 4 % 2:
+                    continue
+                say(f"[edge] {algo} {np.dtype(dtype).name} n={n} n_out={n_out}")
+                got = gpu(ts, algo, y, n_out)
+                exp = orc(oracle_mod, algo, y, n_out)
+                assert np.array_equal(got, exp), (algo, dtype, n, n_out, got, exp)
+
+
+def test_ties_signed_zero_and_extremes(ts, oracle_mod):
+    rng = np.random.default_rng(1)
+    n = 200003
+    base = rng.integers(0, 3, n)
+    cases = {
+        "f64_zeros": np.where(base == 0, -0.0, np.where(base == 1, 0.0, 1.0)),
+        "f32_inf": np.where(base == 0, -np.inf, np.where(base == 1, 0.0, np.inf)).astype(np.float32),
+        "f16_zeros": np.where(base == 0, -0.0, np.where(base == 1, 0.0, -1.0)).astype(np.float16),
+        "i64_ext": np.where(base == 0, np.iinfo(np.int64).min, np.where(base == 1, 0, np.iinfo(np.int64).max)),
+        "u64_ext": np.where(base == 0, 0, np.where(base == 1, 1, 2**64 - 1)).astype(np.uint64),
+        "i8_ext": np.where(base == 0, -128, np.where(base == 1, 0, 127)).astype(np.int8),
+        "const": np.full(n, 7, np.int16),
+    }
+    for name, y in cases.items():
+        for algo in ("minmax", "m4"):
+            for n_out in (2 if algo == "minmax" else 4, 40, 4000, 100000):
+                say(f"[ties] {name} {algo} n_out={n_out}")
+                assert np.array_equal(gpu(ts, algo, y, n_out), orc(oracle_mod, algo, y, n_out)), (name, algo, n_out)
+
+
+@pytest.mark.parametrize("chunk,small", [(4096, -1), (4096, 1), (65536, 100000), (8192, 7), (-1, 1 << 20)])
+def test_tuning_does_not_change_results(ts, oracle_mod, chunk, small):
+    """Chunk size and the one-lane-per-bin threshold only change the work
+    split (bins split over many chunks, many bins per wavefront)."""
+    ts.set_tuning(chunk, small)
+    try:
+        for dtype in (np.float32, np.uint8, np.float64, np.int16):
+            y = S.walk(250007, dtype, seed=5)
+            x = S.timestamps(250007, 50, seed=6)
+            for algo, n_out in (("minmax", 2), ("minmax", 600), ("m4", 40000), ("m4", 8)):
+                for xx in (None, x):
+                    say(f"[tuning] chunk={chunk} small={small} {np.dtype(dtype).name} {algo} {n_out}")
+                    assert np.array_equal(gpu(ts, algo, y, n_out, xx), orc(oracle_mod, algo, y, n_out, xx))
+    finally:
+        ts.set_tuning()
+
+
+@pytest.mark.parametrize("dtype", [np.int8, np.float16, np.float32, np.float64, np.int64])
+def test_misaligned_series_pointer(ts, oracle_mod, dtype):
+    """Slices start at any element: the scan realigns to 16-byte vectors."""
+    y = S.walk(100000, dtype, seed=9)
+    yd = dev(y)
+    for off in range(0, 17):
+        sub = yd[off:]
+        for algo, n_out in (("minmax", 200), ("m4", 400)):
+            say(f"[align] {np.dtype(dtype).name} off={off} {algo}")
+            got = getattr(ts, algo)(sub, n_out).cpu().numpy()
+            assert np.array_equal(got, orc(oracle_mod, algo, y[off:], n_out))
+
+
+def test_cross_dtype_consistency(ts):
+    y0 = np.clip(np.rint(S.walk(150000, np.float64, seed=21) / 20), -60, 120)
+    for algo, n_out in (("minmax", 1000), ("m4", 1000), ("minmaxlttb", 500), ("lttb", 500)):
+        base = gpu(ts, algo, y0.astype(np.float64), n_out)
+        for dt in ALL:
+            yy = y0 + (60 if np.dtype(dt).kind == "u" else 0)
+            say(f"[xdtype] {algo} {np.dtype(dt).name}")
+            assert np.array_equal(gpu(ts, algo, yy.astype(dt), n_out), base), (algo, dt)
+
+
+def test_determinism_repeat(ts):
+    y = dev(S.walk(3_000_001, np.float32, seed=22))
+    for algo, n_out in (("minmax", 1000), ("m4", 2000), ("minmaxlttb", 1000), ("lttb", 1000)):
+        r1 = getattr(ts, algo)(y, n_out).cpu()
+        r2 = getattr(ts, algo)(y, n_out).cpu()
+        assert torch.equal(r1, r2)
+
+
+def test_bin_edges_and_argminmax_steps(ts, oracle_mod):
+    n = 123457
+    y = S.walk(n, np.float32, seed=23)
+    x = S.timestamps(n, 700, seed=24)
+    for nb in (1, 3, 500, 4000):
+        for xx in (None, x, x.astype(np.float64)):
+            say(f"[edges] nb={nb} x={None if xx is None else xx.dtype}")
+            e = ts.bin_edges(dev(y), nb, None if xx is None else dev(xx)).cpu().numpy()
+            assert np.array_equal(e, oracle_mod.edges(n, nb, xx))
+    # caller edges that skip a prefix/suffix and include empty bins
+    edges = np.array([10, 10, 500, 501, 70000, 70000, 123000], np.int64)
+    imin, imax = ts.bin_argminmax(dev(y), dev(edges))
+    for b in range(len(edges) - 1):
+        lo, hi = edges[b], edges[b + 1]
+        if lo == hi:
+            assert imin[b].item() == -1 and imax[b].item() == -1
+        else:
+            assert (imin[b].item(), imax[b].item()) == oracle_mod.argminmax(y, lo, hi)
+
+
+def test_window(ts, oracle_mod):
+    x = S.timestamps(1_000_003, 100, seed=25)
+    xd = dev(x)
+    rng = np.random.default_rng(26)
+    for _ in range(50):
+        a, b = sorted(int(v) for v in rng.integers(-1000, int(x[-1]) + 1000, 2))
+        r = ts.window(xd, a, b).cpu().numpy()
+        assert tuple(r) == oracle_mod.window(x, a, b)
+
+
+# ------------------------------------------------------------------ LTTB
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64, np.int32, np.uint8, np.float16, np.int64])
+@pytest.mark.parametrize("with_x", [False, True])
+def test_lttb_parity(ts, oracle_mod, dtype, with_x):
+    for n, n_out in ((1000, 10), (50000, 1000), (200001, 3), (20000, 4000), (777, 776)):
+        y = S.walk(n, dtype, seed=n % 31)
+        x = S.timestamps(n, 30, seed=7) if with_x else None
+        say(f"[lttb] {np.dtype(dtype).name} x={with_x} n={n} n_out={n_out}")
+        got = gpu(ts, "lttb", y, n_out, x)
+        exp = orc(oracle_mod, "lttb", y, n_out, x)
+        near = stepwise_check(oracle_mod, y, n_out, got, x=x)
+        assert near == 0 and np.array_equal(got, exp)
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64, np.int16, np.uint8, np.float16])
+@pytest.mark.parametrize("xname", ["none", "i64", "f64"])
+def test_minmaxlttb_parity(ts, oracle_mod, dtype, xname):
+    for n, n_out, ratio in ((100000, 500, 4), (1_000_003, 2000, 4), (30000, 1000, 8), (5000, 1000, 4),
+                            (4000, 1000, 4), (250000, 3, 2)):
+        y = S.walk(n, dtype, seed=n % 13)
+        x = xs_for(n, 3)[xname]
+        say(f"[mmlttb] {np.dtype(dtype).name} x={xname} n={n} n_out={n_out} r={ratio}")
+        got = gpu(ts, "minmaxlttb", y, n_out, x, ratio)
+        exp = orc(oracle_mod, "minmaxlttb", y, n_out, x, ratio)
+        assert np.array_equal(got, exp), (dtype, xname, n, n_out)
+
+
+def test_lttb_centres_bit_exact(ts, oracle_mod):
+    for dtype in (np.float32, np.float64, np.int32, np.uint64):
+        y = S.walk(100003, dtype, seed=27)
+        x = S.timestamps(100003, 10, seed=28)
+        for xx in (None, x, x.astype(np.float64)):
+            cx, cy = ts.lttb_centres(dev(y), 700, None if xx is None else dev(xx))
+            ecx, ecy = oracle_mod.lttb_centres(y, 700, x=xx)
+            assert np.array_equal(cx.cpu().numpy(), ecx) and np.array_equal(cy.cpu().numpy(), ecy)
+
+
+# ------------------------------------------------------------------ errors
+
+
+def test_error_paths(ts):
+    from paper_2307_05389_amd import TsArgError, TsError
+    y = dev(S.walk(10000, np.float32, seed=1))
+    with pytest.raises(TsArgError):
+        ts.minmax(y, 1001)
+    with pytest.raises(TsArgError):
+        ts.m4(y, 10)
+    with pytest.raises(TsArgError):
+        ts.minmaxlttb(y, 101, minmax_ratio=1)
+    out = torch.empty(100, dtype=torch.int64, device="cuda")
+    cnt = torch.empty(1, dtype=torch.int64, device="cuda")
+    small_ws = torch.empty(256, dtype=torch.uint8, device="cuda")
+    with pytest.raises(TsError) as ei:
+        ts.downsample_into("minmax", y, 100, out, cnt, workspace=small_ws)
+    assert ei.value.code == -4
+    # nothing was written on error
+    out.fill_(-7)
+    with pytest.raises(TsError):
+        ts.downsample_into("m4", y, 100, out, cnt, workspace=small_ws)
+    torch.cuda.synchronize()
+    assert bool((out == -7).all())
