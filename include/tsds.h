@@ -152,10 +152,18 @@ int ts_window(const ts_series *s, int64_t xa, int64_t xb, int64_t *range, void *
 /* Tuning knobs of the argmin/argmax pass, process-wide: chunk_bytes (a power
  * of two >= 4096; -1 = automatic) is the slice of y one wavefront reduces;
  * bin segments shorter than small_bin elements (-1 = default 128) are reduced
- * one bin per lane instead of one bin per wavefront.  Results never depend on
- * them; workspace sizes do, so query ts_workspace_bytes after a change.  Not
- * thread-safe with concurrent compute calls. */
-int ts_set_tuning(int64_t chunk_bytes, int32_t small_bin);
+ * one bin per lane instead of one bin per wavefront; scan_variant (-1 =
+ * default, 0..3) picks the tile shape (16-byte vectors per lane per tile and
+ * tiles in flight: 0 = 4x2, 1 = 4x1, 2 = 8x1, 3 = 2x2).  Results never depend
+ * on them; workspace sizes do, so query ts_workspace_bytes after a change.
+ * Not thread-safe with concurrent compute calls. */
+int ts_set_tuning(int64_t chunk_bytes, int32_t small_bin, int32_t scan_variant);
+
+/* Timing hook: when both are non-NULL, the next compute calls record the
+ * hipEvent_t `start` on their stream just before the argmin/argmax scan
+ * kernel is launched and `stop` just after it, so a caller can time that
+ * kernel alone.  Pass NULL, NULL to switch it off.  Process-wide. */
+int ts_profile_scan_events(void *start, void *stop);
 
 #ifdef __cplusplus
 }

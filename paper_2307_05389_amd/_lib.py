@@ -69,8 +69,10 @@ def lib():
         L.ts_lttb_centres.restype = ctypes.c_int
         L.ts_window.argtypes = [SP, i64, i64, vp, vp]
         L.ts_window.restype = ctypes.c_int
-        L.ts_set_tuning.argtypes = [i64, i32]
+        L.ts_set_tuning.argtypes = [i64, i32, i32]
         L.ts_set_tuning.restype = ctypes.c_int
+        L.ts_profile_scan_events.argtypes = [vp, vp]
+        L.ts_profile_scan_events.restype = ctypes.c_int
         _lib = L
     return _lib
 

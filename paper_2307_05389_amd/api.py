@@ -107,8 +107,8 @@ def window(x, xa, xb, y=None):
     return r
 
 
-def set_tuning(chunk_bytes=-1, small_bin=-1):
-    """Override the scan's chunk size (power of two >= 4096 bytes) and the
-    segment length below which one lane handles a whole bin; -1 restores the
-    defaults.  Results do not depend on either."""
-    L.check(L.lib().ts_set_tuning(int(chunk_bytes), int(small_bin)))
+def set_tuning(chunk_bytes=-1, small_bin=-1, scan_variant=-1):
+    """Override the scan's chunk size (power of two >= 4096 bytes), the
+    segment length below which one lane handles a whole bin, and the tile
+    shape variant; -1 restores the defaults.  Results do not depend on them."""
+    L.check(L.lib().ts_set_tuning(int(chunk_bytes), int(small_bin), int(scan_variant)))

@@ -18,6 +18,7 @@
 namespace tsds {
 
 size_t lttb_group_count(int64_t n_out);
+int set_scan_variant(int v);
 
 static thread_local std::string g_err;
 
@@ -75,6 +76,8 @@ static int64_t chunk_elems(int ydt, int64_t n) {
   if (bytes < 4096) bytes = 4096;
   return bytes / esz;
 }
+
+static hipEvent_t g_ev_start = nullptr, g_ev_stop = nullptr;
 
 static int32_t small_threshold() { return g_small_override > 0 ? g_small_override : 128; }
 
@@ -226,7 +229,9 @@ static int run_scan(const ts_series &s, int64_t nb, int m4, const ScanPlan &pl, 
   sp.partL = (Partial *)wsp(ws, pl.off_partL);
   sp.partR = (Partial *)wsp(ws, pl.off_partR);
   sp.small = small_threshold();
+  if (g_ev_start && (e = hipEventRecord(g_ev_start, st)) != hipSuccess) return hip_fail(e, "event");
   if ((e = launch_scan(s.y_dtype, sp, st)) != hipSuccess) return hip_fail(e, "scan");
+  if (g_ev_stop && (e = hipEventRecord(g_ev_stop, st)) != hipSuccess) return hip_fail(e, "event");
   MergeParams mp;
   mp.n = s.n;
   mp.shift = sp.shift;
@@ -509,11 +514,20 @@ int ts_window(const ts_series *s, int64_t xa, int64_t xb, int64_t *range, void *
 }
 
 // Tuning knobs (tests use them to show that results do not depend on them).
-int ts_set_tuning(int64_t chunk_bytes, int32_t small_bin) {
+int ts_set_tuning(int64_t chunk_bytes, int32_t small_bin, int32_t scan_variant) {
   if (chunk_bytes > 0 && (chunk_bytes < 4096 || (chunk_bytes & (chunk_bytes - 1))))
     return fail(TS_ERR_ARG, "chunk_bytes must be a power of two >= 4096");
+  if (scan_variant > 3) return fail(TS_ERR_ARG, "scan_variant must be -1..3");
   g_chunk_bytes_override = chunk_bytes;
   g_small_override = small_bin;
+  set_scan_variant(scan_variant);
+  return TS_OK;
+}
+
+int ts_profile_scan_events(void *start, void *stop) {
+  if ((start == nullptr) != (stop == nullptr)) return fail(TS_ERR_NULL, "give both events or neither");
+  g_ev_start = (hipEvent_t)start;
+  g_ev_stop = (hipEvent_t)stop;
   return TS_OK;
 }
 

@@ -213,117 +213,309 @@ __device__ inline void write_result(const ScanParams &p, int64_t c, int64_t bin,
   }
 }
 
-// Whole-wavefront argmin/argmax of y[lo, hi) (lo < hi, wave-uniform).
-// Vector v of the 16-byte aligned base holds elements v*VEC - shift + j.
-// A tile is U vectors per lane, lane-interleaved (fully coalesced).  Per
-// tile the lanes reduce values only; the wavefront min/max comes from DPP;
-// only a tile whose extreme strictly beats the running one is searched for
-// the first position of that value (so ties keep the earlier tile).
+// ---- per-vector reductions and searches ------------------------------------
+//
+// A tile is U 16-byte vectors per lane; vector u of lane l holds tile
+// positions (u*64 + l)*VEC + j, j < VEC, so tile order is (u, lane, j).
+// VecOps<T>::minmax reduces one vector to its minimum and maximum value;
+// narrow types use packed 16-bit min/max (two elements per instruction),
+// bytes being spread into two 16-bit pairs first (signed bytes biased by 0x80
+// so that unsigned order is numeric order).  VecOps<T>::first returns the
+// first j whose element equals a value (VEC if none); bytes and halves test
+// four or two elements per instruction with the zero-lane bit trick.
+
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+typedef short i16x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+
+template <typename V>
+__device__ inline V as2(uint32_t w) { return __builtin_bit_cast(V, w); }
+
+// Lowest 8-bit (B = 8) or 16-bit (B = 16) lane of t that is zero, or -1.
+template <int B>
+__device__ inline int first_zero_lane(uint32_t t) {
+  constexpr uint32_t ONES = B == 8 ? 0x01010101u : 0x00010001u;
+  constexpr uint32_t HIGH = B == 8 ? 0x80808080u : 0x80008000u;
+  const uint32_t z = (t - ONES) & ~t & HIGH;  // lowest set bit marks the lowest zero lane
+  return z ? (int)(__builtin_ctz(z) / B) : -1;
+}
+
+template <typename T> struct VecOps {
+  using C = typename Elem<T>::C;
+  static constexpr int VEC = 16 / (int)sizeof(T);
+  static __device__ inline void minmax(const u32x4 &d, C &mn, C &mx) {
+    mn = extract<T>(d, 0);
+    mx = mn;
+#pragma unroll
+    for (int j = 1; j < VEC; j++) {
+      const C v = extract<T>(d, j);
+      mn = vmin(mn, v);
+      mx = vmax(mx, v);
+    }
+  }
+  static __device__ inline int first(const u32x4 &d, C target) {
+    int r = VEC;
+#pragma unroll
+    for (int j = VEC - 1; j >= 0; j--)
+      if (extract<T>(d, j) == target) r = j;
+    return r;
+  }
+};
+
+template <typename V>
+__device__ inline void pk_vec_minmax(const u32x4 &d, V &a, V &b) {
+  a = as2<V>(d.x);
+  b = a;
+#pragma unroll
+  for (int c = 1; c < 4; c++) {
+    const V v = as2<V>(d[c]);
+    a = __builtin_elementwise_min(a, v);
+    b = __builtin_elementwise_max(b, v);
+  }
+}
+
+template <typename T, uint32_t SIGNMASK>
+__device__ inline int first16(const u32x4 &d, uint32_t pattern16) {
+  const uint32_t pat = pattern16 | (pattern16 << 16);
+#pragma unroll
+  for (int c = 0; c < 4; c++) {
+    const int k = first_zero_lane<16>((d[c] & ~SIGNMASK) ^ pat);
+    if (k >= 0) return 2 * c + k;
+  }
+  return 8;
+}
+
+template <> struct VecOps<uint16_t> {
+  static __device__ inline void minmax(const u32x4 &d, uint32_t &mn, uint32_t &mx) {
+    u16x2 a, b;
+    pk_vec_minmax(d, a, b);
+    mn = a.x < a.y ? a.x : a.y;
+    mx = b.x < b.y ? b.y : b.x;
+  }
+  static __device__ inline int first(const u32x4 &d, uint32_t t) { return first16<uint16_t, 0u>(d, t & 0xffffu); }
+};
+template <> struct VecOps<int16_t> {
+  static __device__ inline void minmax(const u32x4 &d, int32_t &mn, int32_t &mx) {
+    i16x2 a, b;
+    pk_vec_minmax(d, a, b);
+    mn = a.x < a.y ? a.x : a.y;
+    mx = b.x < b.y ? b.y : b.x;
+  }
+  static __device__ inline int first(const u32x4 &d, int32_t t) {
+    return first16<int16_t, 0u>(d, (uint32_t)t & 0xffffu);
+  }
+};
+template <> struct VecOps<half_t> {
+  static __device__ inline void minmax(const u32x4 &d, _Float16 &mn, _Float16 &mx) {
+    f16x2 a, b;
+    pk_vec_minmax(d, a, b);
+    mn = vmin(a.x, a.y);
+    mx = vmax(b.x, b.y);
+  }
+  // Equal values have equal bits except for the two zeros: a zero target
+  // compares magnitudes only.
+  static __device__ inline int first(const u32x4 &d, _Float16 t) {
+    const uint32_t bits = __builtin_bit_cast(uint16_t, t);
+    if ((bits & 0x7fffu) == 0) return first16<half_t, 0x80008000u>(d, 0u);
+    return first16<half_t, 0u>(d, bits);
+  }
+};
+
+// Bytes: w = [b0 b1 b2 b3] -> (b0, b2) and (b1, b3) as 16-bit pairs.
+template <uint32_t BIAS>
+__device__ inline void byte_vec_minmax(const u32x4 &d, uint32_t &mn, uint32_t &mx) {
+  u16x2 a, b;
+#pragma unroll
+  for (int c = 0; c < 4; c++) {
+    const uint32_t w = d[c] ^ BIAS;
+    const u16x2 lo = as2<u16x2>(w & 0x00ff00ffu), hi = as2<u16x2>((w >> 8) & 0x00ff00ffu);
+    const u16x2 m0 = __builtin_elementwise_min(lo, hi), m1 = __builtin_elementwise_max(lo, hi);
+    a = c == 0 ? m0 : __builtin_elementwise_min(a, m0);
+    b = c == 0 ? m1 : __builtin_elementwise_max(b, m1);
+  }
+  mn = a.x < a.y ? a.x : a.y;
+  mx = b.x < b.y ? b.y : b.x;
+}
+__device__ inline int first8(const u32x4 &d, uint32_t raw_byte) {
+  const uint32_t pat = raw_byte * 0x01010101u;
+#pragma unroll
+  for (int c = 0; c < 4; c++) {
+    const int k = first_zero_lane<8>(d[c] ^ pat);
+    if (k >= 0) return 4 * c + k;
+  }
+  return 16;
+}
+template <> struct VecOps<uint8_t> {
+  static __device__ inline void minmax(const u32x4 &d, uint32_t &mn, uint32_t &mx) {
+    byte_vec_minmax<0u>(d, mn, mx);
+  }
+  static __device__ inline int first(const u32x4 &d, uint32_t t) { return first8(d, t & 0xffu); }
+};
+template <> struct VecOps<int8_t> {
+  static __device__ inline void minmax(const u32x4 &d, int32_t &mn, int32_t &mx) {
+    uint32_t a, b;
+    byte_vec_minmax<0x80808080u>(d, a, b);
+    mn = (int32_t)a - 128;
+    mx = (int32_t)b - 128;
+  }
+  static __device__ inline int first(const u32x4 &d, int32_t t) { return first8(d, (uint32_t)t & 0xffu); }
+};
+
+// Masked versions (segment ends): positions outside [rlo, rhi) are ignored.
+template <typename T>
+__device__ inline void vec_minmax_masked(const u32x4 &d, uint32_t q0, uint32_t rlo, uint32_t rhi,
+                                         typename Elem<T>::C &mn, typename Elem<T>::C &mx) {
+  using E = Elem<T>;
+  constexpr int VEC = 16 / (int)sizeof(T);
+  mn = E::highest();
+  mx = E::lowest();
+#pragma unroll
+  for (int j = 0; j < VEC; j++) {
+    const bool ok = q0 + j >= rlo && q0 + j < rhi;
+    const typename E::C v = extract<T>(d, j);
+    mn = vmin(mn, ok ? v : E::highest());
+    mx = vmax(mx, ok ? v : E::lowest());
+  }
+}
+template <typename T>
+__device__ inline int vec_first_masked(const u32x4 &d, typename Elem<T>::C target, uint32_t q0, uint32_t rlo,
+                                       uint32_t rhi) {
+  constexpr int VEC = 16 / (int)sizeof(T);
+  int r = VEC;
+#pragma unroll
+  for (int j = VEC - 1; j >= 0; j--)
+    if (q0 + j >= rlo && q0 + j < rhi && extract<T>(d, j) == target) r = j;
+  return r;
+}
+
+// Running result of one bin segment (wave-uniform).
+template <typename C> struct SegState {
+  C vmn, vmx;
+  int64_t imn, imx;
+  bool has;
+};
+
+// Load tile vt (vectors vt + u*64 + lane); vectors outside [vlo, vhi) are not
+// read (zero).
+template <int U>
+__device__ inline void load_tile(const u32x4 *__restrict__ base, int64_t vt, int64_t vlo, int64_t vhi, int lane,
+                                 u32x4 (&d)[U]) {
+  if (vt >= vlo && vt + (int64_t)kWave * U <= vhi) {
+#pragma unroll
+    for (int u = 0; u < U; u++) d[u] = __builtin_nontemporal_load(base + vt + u * kWave + lane);
+  } else {
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const int64_t v = vt + u * kWave + lane;
+      d[u] = (v >= vlo && v < vhi) ? __builtin_nontemporal_load(base + v) : u32x4{0u, 0u, 0u, 0u};
+    }
+  }
+}
+
+// Tile position of the first element equal to `target` (which some valid
+// element holds): the first vector index u whose per-vector extreme equals
+// the target on some lane, the lowest such lane, then the first j in that
+// lane's vector.  All branches are wave-uniform.
 template <typename T, int U>
-__device__ void wave_segment(const u32x4 *__restrict__ base, int64_t shift, int64_t lo, int64_t hi, int lane,
-                             typename Elem<T>::C &rmn, int64_t &rimn, typename Elem<T>::C &rmx,
-                             int64_t &rimx) {
+__device__ inline uint32_t locate(const u32x4 (&d)[U], const typename Elem<T>::C (&ve)[U], typename Elem<T>::C target,
+                                  bool full, uint32_t rlo, uint32_t rhi, int lane) {
+  constexpr int VEC = 16 / (int)sizeof(T);
+  uint32_t pos = 0;
+  bool found = false;
+#pragma unroll
+  for (int u = 0; u < U; u++) {
+    if (!found) {
+      const uint32_t q0 = (uint32_t)((u * kWave + lane) * VEC);
+      const bool hv = full || (q0 + VEC > rlo && q0 < rhi);
+      const uint64_t m = ballot(hv && ve[u] == target);
+      if (m) {
+        const int l = __builtin_ctzll(m);
+        const int jl = full ? VecOps<T>::first(d[u], target) : vec_first_masked<T>(d[u], target, q0, rlo, rhi);
+        const int j = __builtin_amdgcn_readlane(jl, l);
+        pos = (uint32_t)((u * kWave + l) * VEC + j);
+        found = true;
+      }
+    }
+  }
+  return pos;
+}
+
+// Fold one tile into the running result of segment [lo, hi).  Values are
+// reduced per vector and per lane, DPP gives the wavefront's extremes, and a
+// tile is searched for the position of its extreme only when that extreme
+// strictly beats the running one: equal values in later tiles never replace
+// an earlier index.
+template <typename T, int U>
+__device__ inline void fold_tile(const u32x4 (&d)[U], int64_t vt, int64_t shift, int64_t lo, int64_t hi, int lane,
+                                 SegState<typename Elem<T>::C> &st) {
   using E = Elem<T>;
   using C = typename E::C;
+  constexpr int VEC = 16 / (int)sizeof(T);
+  constexpr int64_t TE = (int64_t)kWave * U * VEC;  // elements per tile
+  const int64_t g0 = vt * VEC - shift;               // index of tile position 0
+  const bool full = g0 >= lo && g0 + TE <= hi;
+  const uint32_t rlo = (uint32_t)(lo > g0 ? lo - g0 : 0);
+  const uint32_t rhi = (uint32_t)(hi < g0 + TE ? hi - g0 : TE);
+  C vm[U], vx[U];
+  if (full) {
+#pragma unroll
+    for (int u = 0; u < U; u++) VecOps<T>::minmax(d[u], vm[u], vx[u]);
+  } else {
+#pragma unroll
+    for (int u = 0; u < U; u++)
+      vec_minmax_masked<T>(d[u], (uint32_t)((u * kWave + lane) * VEC), rlo, rhi, vm[u], vx[u]);
+  }
+  C tmn = vm[0], tmx = vx[0];
+#pragma unroll
+  for (int u = 1; u < U; u++) {
+    tmn = vmin(tmn, vm[u]);
+    tmx = vmax(tmx, vx[u]);
+  }
+  const C wmn = wave_min(tmn), wmx = wave_max(tmx);
+  if (!st.has || wmn < st.vmn) {
+    st.imn = g0 + locate<T, U>(d, vm, wmn, full, rlo, rhi, lane);
+    st.vmn = wmn;
+  }
+  if (!st.has || st.vmx < wmx) {
+    st.imx = g0 + locate<T, U>(d, vx, wmx, full, rlo, rhi, lane);
+    st.vmx = wmx;
+  }
+  st.has = true;
+}
+
+// Whole-wavefront argmin/argmax of y[lo, hi) (lo < hi, wave-uniform), tile by
+// tile with NB tiles in flight.  The first `npre` tiles may already be in buf
+// (the chunk prefetch).
+template <typename T, int U, int NB>
+__device__ void wave_segment(const u32x4 *__restrict__ base, int64_t shift, int64_t lo, int64_t hi, int lane,
+                             u32x4 (&buf)[NB][U], int npre, SegState<typename Elem<T>::C> &st) {
   constexpr int VEC = 16 / (int)sizeof(T);
   constexpr int64_t TV = (int64_t)kWave * U;  // vectors per tile
   const int64_t v_lo = (lo + shift) / VEC;
   const int64_t v_hi = (hi + shift + VEC - 1) / VEC;
-  bool has = false;
-
-  u32x4 buf[2][U];
-  auto interior = [&](int64_t vt) {
-    return vt * VEC - shift >= lo && (vt + TV) * VEC - shift <= hi;
-  };
-  auto load = [&](int64_t vt, u32x4 (&d)[U]) {
-    if (interior(vt)) {
+  const int64_t ntiles = (v_hi - v_lo + TV - 1) / TV;
+  st.has = false;
 #pragma unroll
-      for (int u = 0; u < U; u++) d[u] = __builtin_nontemporal_load(base + vt + u * kWave + lane);
-    } else {
+  for (int k = 0; k < NB; k++)
+    if (k >= npre && k < ntiles) load_tile<U>(base, v_lo + k * TV, v_lo, v_hi, lane, buf[k]);
+  for (int64_t t = 0; t < ntiles; t += NB) {
 #pragma unroll
-      for (int u = 0; u < U; u++) {
-        int64_t v = vt + u * kWave + lane;
-        d[u] = (v >= v_lo && v < v_hi) ? __builtin_nontemporal_load(base + v) : u32x4{0u, 0u, 0u, 0u};
+    for (int k = 0; k < NB; k++) {
+      if (t + k < ntiles) {
+        const int64_t vt = v_lo + (t + k) * TV;
+        fold_tile<T, U>(buf[k], vt, shift, lo, hi, lane, st);
+        if (t + k + NB < ntiles) load_tile<U>(base, vt + NB * TV, v_lo, v_hi, lane, buf[k]);
       }
     }
-  };
-  auto process = [&](int64_t vt, const u32x4 (&d)[U]) {
-    const bool full = interior(vt);
-    C tmn = E::highest(), tmx = E::lowest();
-    if (full) {
-#pragma unroll
-      for (int u = 0; u < U; u++)
-#pragma unroll
-        for (int j = 0; j < VEC; j++) {
-          C xv = extract<T>(d[u], j);
-          tmn = vmin(tmn, xv);
-          tmx = vmax(tmx, xv);
-        }
-    } else {
-#pragma unroll
-      for (int u = 0; u < U; u++)
-#pragma unroll
-        for (int j = 0; j < VEC; j++) {
-          int64_t g = (vt + u * kWave + lane) * VEC + j - shift;
-          bool ok = g >= lo && g < hi;
-          C xv = extract<T>(d[u], j);
-          tmn = vmin(tmn, ok ? xv : E::highest());
-          tmx = vmax(tmx, ok ? xv : E::lowest());
-        }
-    }
-    C wmn = wave_min(tmn), wmx = wave_max(tmx);
-    const int64_t g0 = vt * VEC - shift;  // global index of tile position 0
-    if (!has || wmn < rmn) {
-      uint32_t pos = 0xffffffffu;
-#pragma unroll
-      for (int u = U - 1; u >= 0; u--)
-#pragma unroll
-        for (int j = VEC - 1; j >= 0; j--) {
-          uint32_t q = (uint32_t)((u * kWave + lane) * VEC + j);
-          int64_t g = g0 + q;
-          bool ok = full || (g >= lo && g < hi);
-          if (ok && extract<T>(d[u], j) == wmn) pos = q;
-        }
-      pos = wave_min(pos);
-      rmn = wmn;
-      rimn = g0 + pos;
-    }
-    if (!has || rmx < wmx) {
-      uint32_t pos = 0xffffffffu;
-#pragma unroll
-      for (int u = U - 1; u >= 0; u--)
-#pragma unroll
-        for (int j = VEC - 1; j >= 0; j--) {
-          uint32_t q = (uint32_t)((u * kWave + lane) * VEC + j);
-          int64_t g = g0 + q;
-          bool ok = full || (g >= lo && g < hi);
-          if (ok && extract<T>(d[u], j) == wmx) pos = q;
-        }
-      pos = wave_min(pos);
-      rmx = wmx;
-      rimx = g0 + pos;
-    }
-    has = true;
-  };
-
-  const int64_t ntiles = (v_hi - v_lo + TV - 1) / TV;
-  load(v_lo, buf[0]);
-  int64_t t = 0;
-  for (; t + 1 < ntiles; t += 2) {
-    const int64_t vt = v_lo + t * TV;
-    load(vt + TV, buf[1]);
-    process(vt, buf[0]);
-    if (t + 2 < ntiles) load(vt + 2 * TV, buf[0]);
-    process(vt + TV, buf[1]);
   }
-  if (t < ntiles) process(v_lo + t * TV, buf[0]);
 }
 
-template <typename T, int U>
+template <typename T, int U, int NB>
 __global__ __launch_bounds__(256) void k_scan(ScanParams p) {
   using E = Elem<T>;
   using C = typename E::C;
   constexpr int VEC = 16 / (int)sizeof(T);
+  constexpr int64_t TV = (int64_t)kWave * U;
   const int lane = lane_id();
   const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (c >= p.nchunks) return;
@@ -334,12 +526,20 @@ __global__ __launch_bounds__(256) void k_scan(ScanParams p) {
   int64_t c1 = (c + 1) * p.chunk - p.shift;
   if (c1 > p.n) c1 = p.n;
   if (p.edges) {  // caller bins may not cover the whole series
-    int64_t e0 = p.edges[0], en = p.edges[p.nb];
+    const int64_t e0 = p.edges[0], en = p.edges[p.nb];
     if (c0 < e0) c0 = e0;
     if (c1 > en) c1 = en;
   }
   if (c0 >= c1) return;
-  (void)VEC;
+
+  // Prefetch the chunk's first tiles: they do not depend on the bins, so
+  // their latency overlaps the bin search below.  A big segment starting at
+  // the chunk start (the usual case) consumes them.
+  const int64_t vc0 = (c0 + p.shift) / VEC, vc1 = (c1 + p.shift + VEC - 1) / VEC;
+  u32x4 buf[NB][U];
+#pragma unroll
+  for (int k = 0; k < NB; k++) load_tile<U>(base, vc0 + k * TV, vc0, vc1, lane, buf[k]);
+  int npre = NB;
 
   int64_t b = first_bin(p.edges, p.n, p.nb, c0, lane);
   for (;;) {
@@ -367,11 +567,11 @@ __global__ __launch_bounds__(256) void k_scan(ScanParams p) {
       const int k = __builtin_ctzll(big);
       big &= big - 1;
       const int64_t slo = readlane(lo, k), shi = readlane(hi, k);
-      C vmn, vmx;
-      int64_t imn = 0, imx = 0;
-      wave_segment<T, U>(base, p.shift, slo, shi, lane, vmn, imn, vmx, imx);
+      SegState<C> st;
+      wave_segment<T, U, NB>(base, p.shift, slo, shi, lane, buf, slo == c0 ? npre : 0, st);
+      npre = 0;
       const bool sb = readlane(s, k) < c0, sa = readlane(e, k) > c1;
-      if (lane == 0) write_result<T>(p, c, b + k, sb, sa, vmn, imn, vmx, imx);
+      if (lane == 0) write_result<T>(p, c, b + k, sb, sa, st.vmn, st.imn, st.vmx, st.imx);
     }
     const int64_t e63 = readlane(e, 63);
     if (e63 >= c1 || b + kWave >= p.nb) break;
@@ -379,10 +579,26 @@ __global__ __launch_bounds__(256) void k_scan(ScanParams p) {
   }
 }
 
+// Scan variants (vectors per lane per tile, tiles in flight); the host
+// picks one per element size (TSDS tuning can override).
+static int g_scan_variant = -1;
+
+int set_scan_variant(int v) {
+  g_scan_variant = v;
+  return 0;
+}
+
 template <typename T>
 static hipError_t scan_t(const ScanParams &p, hipStream_t st) {
   dim3 grid((unsigned)((p.nchunks + 3) / 4)), block(256);
-  k_scan<T, 4><<<grid, block, 0, st>>>(p);
+  int v = g_scan_variant;
+  if (v < 0) v = 1;
+  switch (v) {
+    case 0: k_scan<T, 4, 2><<<grid, block, 0, st>>>(p); break;
+    case 1: k_scan<T, 4, 1><<<grid, block, 0, st>>>(p); break;
+    case 2: k_scan<T, 8, 1><<<grid, block, 0, st>>>(p); break;
+    default: k_scan<T, 2, 2><<<grid, block, 0, st>>>(p); break;
+  }
   return hipGetLastError();
 }
 
