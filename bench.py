@@ -167,7 +167,7 @@ def main():
     got = out[: int(cnt.item())].cpu().numpy()
     log(f"[bench] {ms_step:.4f} ms/step, scan kernel {scan_ms:.4f} ms ({achieved:.0f} GB/s)")
 
-    kernel = "k_scan<%s, 4>" % {np.dtype(np.float64): "double", np.dtype(np.float32): "float"}.get(y.dtype, str(y.dtype))
+    variant, chunk_bytes, kernel = L.scan_config(yd.dtype, w["n"] if w["algo"] != "minmaxlttb" else w["n"] - 2)
     traffic = load_traffic(kernel, args.workload)
     res = {
         "metric": "MinMax/M4 input GB/s vs HBM peak",
@@ -187,7 +187,7 @@ def main():
         "points_per_s": round(w["n"] / (ms_step / 1e3), 1),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": kernel, "kernel_ms": round(scan_ms, 5)},
+                     "kernel": kernel, "kernel_ms": round(scan_ms, 5), "chunk_bytes": chunk_bytes},
         "paper_context": "tsdownsample M4 float64 N=1e8 no x, 32-thread Xeon E5-2650 v2: 18.06 ms "
                          "(44.3 GB/s); different hardware and workload",
     }

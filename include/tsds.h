@@ -159,6 +159,10 @@ int ts_window(const ts_series *s, int64_t xa, int64_t xb, int64_t *range, void *
  * Not thread-safe with concurrent compute calls. */
 int ts_set_tuning(int64_t chunk_bytes, int32_t small_bin, int32_t scan_variant);
 
+/* Host-side query: the tile variant and chunk size (bytes) the scan uses for
+ * n elements of y_dtype under the current tuning. */
+int ts_scan_config(int y_dtype, int64_t n, int32_t *variant, int64_t *chunk_bytes);
+
 /* Timing hook: when both are non-NULL, the next compute calls record the
  * hipEvent_t `start` on their stream just before the argmin/argmax scan
  * kernel is launched and `stop` just after it, so a caller can time that

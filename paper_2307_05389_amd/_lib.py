@@ -71,10 +71,26 @@ def lib():
         L.ts_window.restype = ctypes.c_int
         L.ts_set_tuning.argtypes = [i64, i32, i32]
         L.ts_set_tuning.restype = ctypes.c_int
+        L.ts_scan_config.argtypes = [ctypes.c_int, i64, ctypes.POINTER(ctypes.c_int32),
+                                     ctypes.POINTER(ctypes.c_int64)]
+        L.ts_scan_config.restype = ctypes.c_int
         L.ts_profile_scan_events.argtypes = [vp, vp]
         L.ts_profile_scan_events.restype = ctypes.c_int
         _lib = L
     return _lib
+
+
+VARIANT_SHAPE = {0: (4, 2), 1: (4, 1), 2: (8, 1), 3: (2, 2)}
+CTYPE_NAME = {0: "signed char", 1: "short", 2: "int", 3: "long", 4: "unsigned char", 5: "unsigned short",
+              6: "unsigned int", 7: "unsigned long", 8: "tsds::half_t", 9: "float", 10: "double"}
+
+
+def scan_config(dtype, n):
+    """(variant, chunk_bytes, kernel name) the scan uses for n elements."""
+    v, c = ctypes.c_int32(), ctypes.c_int64()
+    check(lib().ts_scan_config(DTYPE_CODES[dtype], int(n), ctypes.byref(v), ctypes.byref(c)))
+    u, nb = VARIANT_SHAPE[v.value]
+    return v.value, c.value, f"tsds::k_scan<{CTYPE_NAME[DTYPE_CODES[dtype]]}, {u}, {nb}>"
 
 
 def check(rc):

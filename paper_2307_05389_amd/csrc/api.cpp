@@ -18,7 +18,6 @@
 namespace tsds {
 
 size_t lttb_group_count(int64_t n_out);
-int set_scan_variant(int v);
 
 static thread_local std::string g_err;
 
@@ -56,26 +55,42 @@ static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 // ------------------------------------------------------------------ tuning
 
-// Elements per chunk of the scan: a power-of-two number of bytes between one
-// tile (64 lanes x 4 x 16 B) and `max_bytes`, aiming at >= `target` chunks so
-// that every CU holds many wavefronts.  TSDS_CHUNK_BYTES overrides.
+// Scan launch shape per dtype: tile variant (see launch_scan) and chunk bytes,
+// from sweeps on MI355X over 800 MB inputs (each pair is the fastest measured
+// for that element type).  Smaller inputs get smaller chunks so that there
+// are at least ~4096 chunks (one wavefront each) when possible.
+struct ScanShape {
+  int32_t variant;
+  int64_t chunk_bytes;
+};
+
+static ScanShape default_shape(int ydt) {
+  switch (ydt) {
+    case TS_U8: return {3, 16384};
+    case TS_I8: return {0, 65536};
+    case TS_I16: case TS_U16: case TS_F16: return {0, 16384};
+    case TS_I32: case TS_U32: case TS_F32: return {2, 16384};
+    default: return {2, 32768};
+  }
+}
+
 static int64_t g_chunk_bytes_override = -1;
 static int32_t g_small_override = -1;
+static int32_t g_variant_override = -1;
 
-static int64_t chunk_elems(int ydt, int64_t n) {
-  const int64_t esz = (int64_t)elem_size(ydt);
-  int64_t bytes;
+static ScanShape scan_shape(int ydt, int64_t n) {
+  ScanShape sh = default_shape(ydt);
+  if (g_variant_override >= 0) sh.variant = g_variant_override;
   if (g_chunk_bytes_override > 0) {
-    bytes = g_chunk_bytes_override;
+    sh.chunk_bytes = g_chunk_bytes_override;
   } else {
-    const int64_t total = n * esz;
-    const int64_t target = 8192, lo = 4096, hi = 65536;
-    bytes = lo;
-    while (bytes * 2 <= hi && total / (bytes * 2) >= target) bytes *= 2;
+    const int64_t total = n * (int64_t)elem_size(ydt);
+    while (sh.chunk_bytes > 4096 && total / sh.chunk_bytes < 4096) sh.chunk_bytes /= 2;
   }
-  if (bytes < 4096) bytes = 4096;
-  return bytes / esz;
+  return sh;
 }
+
+static int64_t chunk_elems(int ydt, int64_t n) { return scan_shape(ydt, n).chunk_bytes / (int64_t)elem_size(ydt); }
 
 static hipEvent_t g_ev_start = nullptr, g_ev_stop = nullptr;
 
@@ -229,6 +244,7 @@ static int run_scan(const ts_series &s, int64_t nb, int m4, const ScanPlan &pl, 
   sp.partL = (Partial *)wsp(ws, pl.off_partL);
   sp.partR = (Partial *)wsp(ws, pl.off_partR);
   sp.small = small_threshold();
+  sp.variant = scan_shape(s.y_dtype, s.n).variant;
   if (g_ev_start && (e = hipEventRecord(g_ev_start, st)) != hipSuccess) return hip_fail(e, "event");
   if ((e = launch_scan(s.y_dtype, sp, st)) != hipSuccess) return hip_fail(e, "scan");
   if (g_ev_stop && (e = hipEventRecord(g_ev_stop, st)) != hipSuccess) return hip_fail(e, "event");
@@ -464,6 +480,7 @@ int ts_bin_argminmax(const ts_series *s, const int64_t *edges, int64_t nb, int64
   sp.partL = (Partial *)wsp(ws, pl.off_partL);
   sp.partR = (Partial *)wsp(ws, pl.off_partR);
   sp.small = small_threshold();
+  sp.variant = scan_shape(s->y_dtype, s->n).variant;
   hipError_t e;
   if ((e = launch_scan(s->y_dtype, sp, st)) != hipSuccess) return hip_fail(e, "scan");
   MergeParams mp{};
@@ -520,7 +537,16 @@ int ts_set_tuning(int64_t chunk_bytes, int32_t small_bin, int32_t scan_variant) 
   if (scan_variant > 3) return fail(TS_ERR_ARG, "scan_variant must be -1..3");
   g_chunk_bytes_override = chunk_bytes;
   g_small_override = small_bin;
-  set_scan_variant(scan_variant);
+  g_variant_override = scan_variant;
+  return TS_OK;
+}
+
+int ts_scan_config(int y_dtype, int64_t n, int32_t *variant, int64_t *chunk_bytes) {
+  if (elem_size(y_dtype) == 0) return fail(TS_ERR_DTYPE, "y dtype %d is not a ts dtype", y_dtype);
+  if (!variant || !chunk_bytes) return fail(TS_ERR_NULL, "variant / chunk_bytes is NULL");
+  const ScanShape sh = scan_shape(y_dtype, n);
+  *variant = sh.variant;
+  *chunk_bytes = sh.chunk_bytes;
   return TS_OK;
 }
 

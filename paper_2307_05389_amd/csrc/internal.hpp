@@ -26,6 +26,7 @@ struct ScanParams {
   Partial *partL;         // [nchunks] bin that started before the chunk
   Partial *partR;         // [nchunks] bin that continues after the chunk
   int32_t small;          // segments shorter than this: one lane per bin
+  int32_t variant;        // tile shape (see launch_scan)
 };
 
 struct MergeParams {

@@ -579,21 +579,11 @@ __global__ __launch_bounds__(256) void k_scan(ScanParams p) {
   }
 }
 
-// Scan variants (vectors per lane per tile, tiles in flight); the host
-// picks one per element size (TSDS tuning can override).
-static int g_scan_variant = -1;
-
-int set_scan_variant(int v) {
-  g_scan_variant = v;
-  return 0;
-}
-
+// Tile shapes: 16-byte vectors per lane per tile x tiles in flight.
 template <typename T>
 static hipError_t scan_t(const ScanParams &p, hipStream_t st) {
   dim3 grid((unsigned)((p.nchunks + 3) / 4)), block(256);
-  int v = g_scan_variant;
-  if (v < 0) v = 1;
-  switch (v) {
+  switch (p.variant) {
     case 0: k_scan<T, 4, 2><<<grid, block, 0, st>>>(p); break;
     case 1: k_scan<T, 4, 1><<<grid, block, 0, st>>>(p); break;
     case 2: k_scan<T, 8, 1><<<grid, block, 0, st>>>(p); break;
