@@ -149,6 +149,64 @@ int ts_lttb_centres(const ts_series *s, const int64_t *sel, int64_t m, int64_t n
  * device int64[2] `range` (integer x only). */
 int ts_window(const ts_series *s, int64_t xa, int64_t xb, int64_t *range, void *stream);
 
+/* ---- Batched mode: many series in one pass ---------------------------- */
+
+/* One task: a series, its algorithm (TS_MINMAX, TS_M4 or TS_MINMAXLTTB),
+ * n_out, minmax_ratio (MinMaxLTTB only, 1..30) and the first slot of its
+ * output in the batch's out_idx array (it writes up to n_out indices there
+ * and its count to counts[task]). */
+typedef struct {
+  int32_t algo;
+  ts_series series;
+  int64_t n_out;
+  int64_t minmax_ratio;
+  int64_t out_offset;
+} ts_task;
+
+typedef struct ts_plan ts_plan;
+
+/* Validates every task (same rules as the single-series calls) and builds
+ * the per-series offset tables: every series is cut into equal-byte chunks
+ * of one global work list and its bins into one global list of bin slots.
+ * The plan keeps the series pointers (they must stay valid while the plan is
+ * used) and owns a small device table (about 160 B per task + 4 B per bin)
+ * that it allocates here and frees in ts_plan_free.  *plan = NULL on error. */
+int ts_batch_plan(const ts_task *tasks, int64_t n_tasks, ts_plan **plan);
+
+/* Workspace bytes ts_batch_run needs (any tuning), and the length out_idx
+ * must have (max over tasks of out_offset + n_out). */
+size_t ts_batch_workspace_bytes(const ts_plan *plan);
+int64_t ts_batch_out_size(const ts_plan *plan);
+
+/* Runs every task: one persistent argmin/argmax launch over the whole work
+ * list (mixed dtypes and algorithms), one merge launch over all bins, one
+ * compaction launch (one workgroup per task) and, if there are MinMaxLTTB
+ * tasks, one LTTB launch (one workgroup per task).  Outputs are identical to
+ * one single-series call per task.  use_graph != 0: the launches are captured
+ * once into a hipGraph (re-captured when out_idx, counts or ws change) and
+ * replayed with one hipGraphLaunch on `stream`.  out_idx: device int64
+ * [ts_batch_out_size]; counts: device int64[n_tasks]; ws: device,
+ * 256-byte aligned, >= ts_batch_workspace_bytes. */
+int ts_batch_run(ts_plan *plan, int64_t *out_idx, int64_t *counts, void *ws, size_t ws_bytes, void *stream,
+                 int use_graph);
+
+/* Tuning of a plan: chunk_bytes (power of two, 4 KiB..4 MiB) per work item,
+ * small_bin (segments shorter than this are reduced one bin per lane, i.e.
+ * up to 64 bins per wavefront) and the persistent grid size in workgroups of
+ * four wavefronts.  Results do not depend on them. */
+int ts_batch_set_tuning(ts_plan *plan, int64_t chunk_bytes, int32_t small_bin, int64_t grid_blocks);
+int ts_batch_get_tuning(const ts_plan *plan, int64_t *chunk_bytes, int32_t *small_bin, int64_t *grid_blocks);
+
+/* Autotuner: times every candidate (chunk 8..64 KiB x small_bin 32/128/512 x
+ * grid 4/6/8 workgroups per CU) on the caller's buffers, keeps the fastest,
+ * and synchronises `stream`.  With cache_path (a text file), the choice is
+ * stored per batch signature (the dtype / algorithm / size-class mix) and
+ * reused without timing.  Results never change. */
+int ts_batch_autotune(ts_plan *plan, int64_t *out_idx, int64_t *counts, void *ws, size_t ws_bytes, void *stream,
+                      const char *cache_path);
+
+void ts_plan_free(ts_plan *plan);
+
 /* Tuning knobs of the argmin/argmax pass, process-wide: chunk_bytes (a power
  * of two >= 4096; -1 = automatic) is the slice of y one wavefront reduces;
  * bin segments shorter than small_bin elements (-1 = default 128) are reduced

@@ -15,6 +15,7 @@ from .api import (  # noqa: F401
     set_tuning, window, workspace_bytes,
 )
 from ._lib import TsArgError, TsError, lib  # noqa: F401
+from .batch import Batch  # noqa: F401
 
 __all__ = ["minmax", "m4", "lttb", "minmaxlttb", "downsample_into", "workspace_bytes", "bin_edges",
-           "bin_argminmax", "lttb_centres", "window", "set_tuning", "TsError", "TsArgError"]
+           "bin_argminmax", "lttb_centres", "window", "set_tuning", "Batch", "TsError", "TsArgError"]

@@ -351,6 +351,10 @@ static bool lttb_small_buckets(int64_t m, int64_t n_out) {
   return maxb <= 32 && m <= (int64_t)1 << 30;
 }
 
+int api_fail(int code, const char *msg) { return fail(code, "%s", msg); }
+int api_check_series(const ts_series *s) { return check_series(s); }
+int api_check_nout(int algo, int64_t n_out, int64_t ratio) { return check_nout(algo, n_out, ratio); }
+
 }  // namespace tsds
 
 using namespace tsds;

@@ -1,0 +1,436 @@
+// api_batch.cpp -- batched downsampling: plan (per-series offset tables and
+// workspace layout), eager or hipGraph launch, and an autotuner over the
+// chunk size, the one-lane-per-bin threshold and the persistent grid size.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+#include "internal.hpp"
+#include "tsds.h"
+
+namespace tsds {
+
+int api_fail(int code, const char *msg);
+int api_check_series(const ts_series *s);
+int api_check_nout(int algo, int64_t n_out, int64_t ratio);
+size_t lttb_group_count(int64_t n_out);
+
+static size_t al256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+}  // namespace tsds
+
+using namespace tsds;
+
+struct ts_plan {
+  std::vector<ts_task> in;
+  std::vector<BatchTask> tasks;
+  std::vector<int32_t> slot_task, lttb_tasks;
+  int64_t total_chunks = 0, total_slots = 0;
+  size_t ws_bytes = 0;      // for the largest chunk count in the tuning space
+  int64_t out_needed = 0;   // max(out_offset + n_out)
+  bool any_x = false;
+  int64_t max_m = 0;        // largest MinMaxLTTB candidate capacity
+  // tuning
+  int64_t chunk_bytes = 16384;
+  int32_t small = 128;
+  int64_t grid_blocks = 0;
+  // device table
+  void *d_table = nullptr;
+  size_t table_bytes = 0;
+  int device = 0;
+  // graph
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  const void *g_out = nullptr, *g_counts = nullptr, *g_ws = nullptr;
+};
+
+namespace {
+
+const int64_t kMinChunk = 4096;
+
+size_t esize(int dt) { return elem_size(dt); }
+
+// Lay out every task for chunk size `chunk_bytes`; returns the workspace size.
+size_t layout(ts_plan *p, int64_t chunk_bytes) {
+  p->tasks.clear();
+  p->slot_task.clear();
+  p->lttb_tasks.clear();
+  p->total_chunks = 0;
+  p->total_slots = 0;
+  p->any_x = false;
+  p->max_m = 0;
+  size_t o = 0;
+  int64_t ti = 0;
+  for (const ts_task &in : p->in) {
+    BatchTask t;
+    memset(&t, 0, sizeof t);
+    const ts_series &s = in.series;
+    t.algo = in.algo;
+    t.ydt = s.y_dtype;
+    t.xdt = s.x ? s.x_dtype : TS_NONE;
+    t.n_out = in.n_out;
+    t.out_offset = in.out_offset;
+    t.yf = s.y;
+    t.xf = s.x;
+    t.nf = s.n;
+    t.y = s.y;
+    t.x = s.x;
+    t.n = s.n;
+    t.mode = 0;
+    if (s.n <= in.n_out) {
+      t.mode = 1;
+    } else if (in.algo == TS_MINMAXLTTB) {
+      const int64_t npre = in.n_out * in.minmax_ratio;
+      if (s.n - 2 <= npre) {
+        t.mode = 2;
+      } else {
+        t.y = (const char *)s.y + esize(s.y_dtype);
+        t.x = s.x ? (const char *)s.x + esize(s.x_dtype) : nullptr;
+        t.n = s.n - 2;
+      }
+    }
+    t.chunk_begin = p->total_chunks;
+    t.slot_begin = p->total_slots;
+    if (t.mode == 0) {
+      const int64_t es = (int64_t)esize(t.ydt);
+      t.nb = in.algo == TS_MINMAX ? in.n_out / 2 : in.algo == TS_M4 ? in.n_out / 4 : in.n_out * in.minmax_ratio / 2;
+      t.chunk = chunk_bytes / es;
+      t.shift = (int64_t)(((uintptr_t)t.y & 15) / (uintptr_t)es);
+      t.nchunks = (t.n + t.shift + t.chunk - 1) / t.chunk;
+      // workspace regions (sized for the smallest chunk of the tuning space)
+      const int64_t nch_max = (t.n + 16 + kMinChunk / es - 1) / (kMinChunk / es);
+      if (t.x) {
+        t.o_edges = (int64_t)o;
+        o = al256(o + 8 * (size_t)(t.nb + 1));
+        p->any_x = true;
+      }
+      t.o_binres = (int64_t)o;
+      o = al256(o + 16 * (size_t)t.nb);
+      t.o_partL = (int64_t)o;
+      o = al256(o + sizeof(Partial) * (size_t)nch_max);
+      t.o_partR = (int64_t)o;
+      o = al256(o + sizeof(Partial) * (size_t)nch_max);
+      t.o_sel = (int64_t)o;
+      o = al256(o + 32 * (size_t)t.nb);
+      t.o_cnt = (int64_t)o;
+      o = al256(o + 8 * (size_t)t.nb);
+      p->total_chunks += t.nchunks;
+      p->total_slots += t.nb + 1;
+      for (int64_t k = 0; k < t.nb + 1; k++) p->slot_task.push_back((int32_t)ti);
+    }
+    if (in.algo == TS_MINMAXLTTB && t.mode != 1) {
+      t.m_max = t.mode == 0 ? in.n_out * in.minmax_ratio + 2 : s.n;
+      if (t.mode == 0) {
+        t.o_cand = (int64_t)o;
+        o = al256(o + 8 * (size_t)t.m_max);
+        t.o_m = (int64_t)o;
+        o = al256(o + 8);
+      }
+      t.o_cx = (int64_t)o;
+      o = al256(o + 8 * (size_t)(in.n_out - 2));
+      t.o_cy = (int64_t)o;
+      o = al256(o + 8 * (size_t)(in.n_out - 2));
+      t.o_next = (int64_t)o;
+      o = al256(o + 8 * (size_t)t.m_max);
+      t.o_entry = (int64_t)o;
+      o = al256(o + 4 * (lttb_group_count(in.n_out) + 1));
+      p->max_m = std::max(p->max_m, t.m_max);
+    }
+    if (in.algo == TS_MINMAXLTTB) p->lttb_tasks.push_back((int32_t)ti);
+    p->tasks.push_back(t);
+    ti++;
+  }
+  return o;
+}
+
+int upload(ts_plan *p) {
+  const size_t a = al256(sizeof(BatchTask) * p->tasks.size());
+  const size_t b = al256(sizeof(int32_t) * p->slot_task.size());
+  const size_t c = al256(sizeof(int32_t) * p->lttb_tasks.size());
+  const size_t need = std::max<size_t>(a + b + c, 256);
+  hipError_t e;
+  if (need > p->table_bytes) {
+    if (p->d_table) (void)hipFree(p->d_table);
+    p->d_table = nullptr;
+    if ((e = hipMalloc(&p->d_table, need)) != hipSuccess) return api_fail(TS_ERR_HIP, "plan table allocation failed");
+    p->table_bytes = need;
+  }
+  std::vector<char> h(need, 0);
+  memcpy(h.data(), p->tasks.data(), sizeof(BatchTask) * p->tasks.size());
+  memcpy(h.data() + a, p->slot_task.data(), sizeof(int32_t) * p->slot_task.size());
+  memcpy(h.data() + a + b, p->lttb_tasks.data(), sizeof(int32_t) * p->lttb_tasks.size());
+  if ((e = hipMemcpy(p->d_table, h.data(), need, hipMemcpyHostToDevice)) != hipSuccess)
+    return api_fail(TS_ERR_HIP, "plan table upload failed");
+  return TS_OK;
+}
+
+BatchArgs args(const ts_plan *p, int64_t *out, int64_t *counts, void *ws) {
+  BatchArgs a;
+  const size_t ta = al256(sizeof(BatchTask) * p->tasks.size());
+  const size_t tb = al256(sizeof(int32_t) * p->slot_task.size());
+  a.tasks = (const BatchTask *)p->d_table;
+  a.slot_task = (const int32_t *)((const char *)p->d_table + ta);
+  a.lttb_tasks = (const int32_t *)((const char *)p->d_table + ta + tb);
+  a.ntasks = (int64_t)p->tasks.size();
+  a.total_chunks = p->total_chunks;
+  a.total_slots = p->total_slots;
+  a.n_lttb = (int64_t)p->lttb_tasks.size();
+  a.ws = (char *)ws;
+  a.out = out;
+  a.counts = counts;
+  a.small = p->small;
+  a.lds_m = 16384;
+  a.lds_ok = p->max_m <= a.lds_m ? 1 : 0;
+  if (a.lds_ok) a.lds_m = std::max<int64_t>(p->max_m, 1);
+  return a;
+}
+
+int enqueue(const ts_plan *p, int64_t *out, int64_t *counts, void *ws, hipStream_t st) {
+  const BatchArgs a = args(p, out, counts, ws);
+  hipError_t e;
+  if (p->any_x && (e = launch_batch_edges(a, st)) != hipSuccess) return api_fail(TS_ERR_HIP, "batch edges launch failed");
+  if ((e = launch_batch_scan(a, p->grid_blocks, st)) != hipSuccess) return api_fail(TS_ERR_HIP, "batch scan launch failed");
+  if ((e = launch_batch_merge(a, st)) != hipSuccess) return api_fail(TS_ERR_HIP, "batch merge launch failed");
+  if ((e = launch_batch_compact(a, st)) != hipSuccess) return api_fail(TS_ERR_HIP, "batch compact launch failed");
+  if ((e = launch_batch_lttb(a, st)) != hipSuccess) return api_fail(TS_ERR_HIP, "batch lttb launch failed");
+  return TS_OK;
+}
+
+void drop_graph(ts_plan *p) {
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  p->exec = nullptr;
+  p->graph = nullptr;
+  p->g_out = p->g_counts = p->g_ws = nullptr;
+}
+
+int check_run(const ts_plan *p, const int64_t *out, const int64_t *counts, const void *ws, size_t ws_bytes) {
+  if (!p) return api_fail(TS_ERR_NULL, "plan is NULL");
+  if (!counts || (!out && p->out_needed > 0)) return api_fail(TS_ERR_NULL, "out_idx / counts is NULL");
+  if (p->ws_bytes > 0) {
+    if (!ws) return api_fail(TS_ERR_WORKSPACE, "workspace is NULL");
+    if ((uintptr_t)ws % 256) return api_fail(TS_ERR_WORKSPACE, "workspace is not 256-byte aligned");
+    if (ws_bytes < p->ws_bytes) return api_fail(TS_ERR_WORKSPACE, "workspace smaller than ts_batch_workspace_bytes");
+  }
+  return TS_OK;
+}
+
+std::string signature(const ts_plan *p) {
+  // dtype / algo / size-class histogram of the batch
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](uint64_t v) {
+    h ^= v;
+    h *= 1099511628211ull;
+  };
+  for (const ts_task &t : p->in) {
+    int64_t lg = 0;
+    while ((1ll << lg) < t.series.n) lg++;
+    mix((uint64_t)t.algo);
+    mix((uint64_t)(t.series.y_dtype + 16));
+    mix((uint64_t)lg);
+    mix((uint64_t)(t.series.x != nullptr));
+  }
+  char buf[64];
+  snprintf(buf, sizeof buf, "%016llx-%zu", (unsigned long long)h, p->in.size());
+  return buf;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ts_batch_plan(const ts_task *tasks, int64_t n_tasks, ts_plan **out_plan) {
+  if (!out_plan) return api_fail(TS_ERR_NULL, "out_plan is NULL");
+  *out_plan = nullptr;
+  if (n_tasks < 0 || n_tasks > (1 << 24)) return api_fail(TS_ERR_ARG, "n_tasks out of range");
+  if (n_tasks > 0 && !tasks) return api_fail(TS_ERR_NULL, "tasks is NULL");
+  ts_plan *p = new ts_plan();
+  for (int64_t i = 0; i < n_tasks; i++) {
+    const ts_task &t = tasks[i];
+    int rc;
+    if (t.algo != TS_MINMAX && t.algo != TS_M4 && t.algo != TS_MINMAXLTTB) {
+      delete p;
+      return api_fail(TS_ERR_ARG, "batched tasks are MinMax, M4 or MinMaxLTTB");
+    }
+    if ((rc = api_check_series(&t.series)) || (rc = api_check_nout(t.algo, t.n_out, t.minmax_ratio))) {
+      delete p;
+      return rc;
+    }
+    if (t.algo == TS_MINMAXLTTB && t.minmax_ratio > 30) {
+      delete p;
+      return api_fail(TS_ERR_ARG, "batched MinMaxLTTB needs minmax_ratio <= 30");
+    }
+    if (t.out_offset < 0) {
+      delete p;
+      return api_fail(TS_ERR_ARG, "out_offset < 0");
+    }
+    p->out_needed = std::max(p->out_needed, t.out_offset + t.n_out);
+    p->in.push_back(t);
+  }
+  int cus = 256;
+  if (hipGetDevice(&p->device) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess) {
+    delete p;
+    return api_fail(TS_ERR_HIP, "no HIP device");
+  }
+  p->grid_blocks = (int64_t)cus * 6;
+  p->ws_bytes = layout(p, kMinChunk);        // largest chunk count of the tuning space
+  layout(p, p->chunk_bytes);
+  int rc = upload(p);
+  if (rc) {
+    if (p->d_table) (void)hipFree(p->d_table);
+    delete p;
+    return rc;
+  }
+  *out_plan = p;
+  return TS_OK;
+}
+
+size_t ts_batch_workspace_bytes(const ts_plan *p) { return p ? p->ws_bytes : 0; }
+
+int64_t ts_batch_out_size(const ts_plan *p) { return p ? p->out_needed : 0; }
+
+int ts_batch_set_tuning(ts_plan *p, int64_t chunk_bytes, int32_t small_bin, int64_t grid_blocks) {
+  if (!p) return api_fail(TS_ERR_NULL, "plan is NULL");
+  if (chunk_bytes < kMinChunk || chunk_bytes > (1 << 22) || (chunk_bytes & (chunk_bytes - 1)))
+    return api_fail(TS_ERR_ARG, "chunk_bytes must be a power of two in [4096, 4 MiB]");
+  if (small_bin < 1) return api_fail(TS_ERR_ARG, "small_bin must be >= 1");
+  if (grid_blocks < 1) return api_fail(TS_ERR_ARG, "grid_blocks must be >= 1");
+  p->chunk_bytes = chunk_bytes;
+  p->small = small_bin;
+  p->grid_blocks = grid_blocks;
+  layout(p, chunk_bytes);
+  drop_graph(p);
+  return upload(p);
+}
+
+int ts_batch_get_tuning(const ts_plan *p, int64_t *chunk_bytes, int32_t *small_bin, int64_t *grid_blocks) {
+  if (!p || !chunk_bytes || !small_bin || !grid_blocks) return api_fail(TS_ERR_NULL, "NULL argument");
+  *chunk_bytes = p->chunk_bytes;
+  *small_bin = p->small;
+  *grid_blocks = p->grid_blocks;
+  return TS_OK;
+}
+
+int ts_batch_run(ts_plan *p, int64_t *out_idx, int64_t *counts, void *ws, size_t ws_bytes, void *stream,
+                 int use_graph) {
+  int rc;
+  if ((rc = check_run(p, out_idx, counts, ws, ws_bytes))) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  if (!use_graph) return enqueue(p, out_idx, counts, ws, st);
+  if (!p->exec || p->g_out != out_idx || p->g_counts != counts || p->g_ws != ws) {
+    drop_graph(p);
+    hipError_t e;
+    if (!p->cap_stream && (e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking)) != hipSuccess)
+      return api_fail(TS_ERR_HIP, "capture stream creation failed");
+    if ((e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+      return api_fail(TS_ERR_HIP, "graph capture failed to start");
+    rc = enqueue(p, out_idx, counts, ws, p->cap_stream);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(p->cap_stream, &g);
+    if (rc) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    if (e != hipSuccess) return api_fail(TS_ERR_HIP, "graph capture failed");
+    p->graph = g;
+    if ((e = hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0)) != hipSuccess) {
+      drop_graph(p);
+      return api_fail(TS_ERR_HIP, "graph instantiation failed");
+    }
+    p->g_out = out_idx;
+    p->g_counts = counts;
+    p->g_ws = ws;
+  }
+  hipError_t e = hipGraphLaunch(p->exec, st);
+  if (e != hipSuccess) return api_fail(TS_ERR_HIP, "graph launch failed");
+  return TS_OK;
+}
+
+// Times each (chunk, small-bin threshold, grid) candidate on the caller's
+// buffers and keeps the fastest.  With a cache path, results are stored per
+// batch signature (dtype / algorithm / size-class mix) and reused.
+int ts_batch_autotune(ts_plan *p, int64_t *out_idx, int64_t *counts, void *ws, size_t ws_bytes, void *stream,
+                      const char *cache_path) {
+  int rc;
+  if ((rc = check_run(p, out_idx, counts, ws, ws_bytes))) return rc;
+  const std::string sig = signature(p);
+  if (cache_path) {
+    FILE *f = fopen(cache_path, "r");
+    if (f) {
+      char key[128];
+      long long cb, gb;
+      int sm;
+      while (fscanf(f, "%127s %lld %d %lld", key, &cb, &sm, &gb) == 4) {
+        if (sig == key) {
+          fclose(f);
+          return ts_batch_set_tuning(p, cb, sm, gb);
+        }
+      }
+      fclose(f);
+    }
+  }
+  hipStream_t st = (hipStream_t)stream;
+  int cus = 256;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess)
+    return api_fail(TS_ERR_HIP, "device query failed");
+  const int64_t chunks[] = {8192, 16384, 32768, 65536};
+  const int32_t smalls[] = {32, 128, 512};
+  const int64_t grids[] = {(int64_t)cus * 4, (int64_t)cus * 6, (int64_t)cus * 8};
+  hipEvent_t a, b;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
+    return api_fail(TS_ERR_HIP, "event creation failed");
+  float best = 1e30f;
+  int64_t bc = p->chunk_bytes, bg = p->grid_blocks;
+  int32_t bs = p->small;
+  for (int64_t cb : chunks)
+    for (int32_t sm : smalls)
+      for (int64_t gb : grids) {
+        if ((rc = ts_batch_set_tuning(p, cb, sm, gb))) break;
+        if ((rc = enqueue(p, out_idx, counts, ws, st))) break;  // warm-up
+        if (hipEventRecord(a, st) != hipSuccess) { rc = api_fail(TS_ERR_HIP, "event record failed"); break; }
+        for (int r = 0; r < 3 && !rc; r++) rc = enqueue(p, out_idx, counts, ws, st);
+        if (rc) break;
+        float ms = 0;
+        if (hipEventRecord(b, st) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
+            hipEventElapsedTime(&ms, a, b) != hipSuccess) {
+          rc = api_fail(TS_ERR_HIP, "event timing failed");
+          break;
+        }
+        if (ms < best) {
+          best = ms;
+          bc = cb;
+          bs = sm;
+          bg = gb;
+        }
+      }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (rc) return rc;
+  if ((rc = ts_batch_set_tuning(p, bc, bs, bg))) return rc;
+  if (cache_path) {
+    FILE *f = fopen(cache_path, "a");
+    if (f) {
+      fprintf(f, "%s %lld %d %lld\n", sig.c_str(), (long long)bc, bs, (long long)bg);
+      fclose(f);
+    }
+  }
+  return TS_OK;
+}
+
+void ts_plan_free(ts_plan *p) {
+  if (!p) return;
+  drop_graph(p);
+  if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+  if (p->d_table) (void)hipFree(p->d_table);
+  delete p;
+}
+
+}  // extern "C"

@@ -92,3 +92,47 @@ hipError_t launch_lttb_small(const LttbParams &p, hipStream_t st);
 hipError_t launch_lttb_seq(const LttbParams &p, hipStream_t st);
 
 }  // namespace tsds
+
+namespace tsds {
+
+// One task of a batched launch (device table entry).  Offsets (o_*) are
+// byte offsets into the workspace; out_offset indexes the output array.
+struct BatchTask {
+  const void *y;        // scanned series (the interior for MinMaxLTTB)
+  const void *x;        // NULL if no x
+  int64_t n;
+  int32_t ydt, xdt;
+  int32_t algo;         // TS_MINMAX, TS_M4, TS_MINMAXLTTB
+  int32_t mode;         // 0: scan; 1: n <= n_out (all indices); 2: MinMaxLTTB without preselection
+  int64_t shift, chunk, nchunks, nb;
+  int64_t chunk_begin;  // first global work item (chunk) of this task
+  int64_t slot_begin;   // first global bin slot (nb + 1 slots per task)
+  int64_t n_out, out_offset;
+  int64_t o_edges, o_binres, o_partL, o_partR, o_sel, o_cnt;
+  int64_t o_cand, o_m, o_cx, o_cy, o_next, o_entry;
+  const void *yf;       // full series (MinMaxLTTB's LTTB step)
+  const void *xf;
+  int64_t nf;
+  int64_t m_max;        // candidates capacity
+};
+
+struct BatchArgs {
+  const BatchTask *tasks;
+  const int32_t *slot_task;  // [total_slots] task of each global bin slot
+  const int32_t *lttb_tasks; // [n_lttb] indices of MinMaxLTTB tasks
+  int64_t ntasks, total_chunks, total_slots, n_lttb;
+  char *ws;
+  int64_t *out;
+  int64_t *counts;
+  int32_t small;
+  int32_t lds_ok;            // LTTB maps fit in LDS for every task
+  int64_t lds_m;             // m capacity of the LDS maps
+};
+
+hipError_t launch_batch_edges(const BatchArgs &a, hipStream_t st);
+hipError_t launch_batch_scan(const BatchArgs &a, int64_t grid_blocks, hipStream_t st);
+hipError_t launch_batch_merge(const BatchArgs &a, hipStream_t st);
+hipError_t launch_batch_compact(const BatchArgs &a, hipStream_t st);
+hipError_t launch_batch_lttb(const BatchArgs &a, hipStream_t st);
+
+}  // namespace tsds

@@ -30,120 +30,9 @@
 
 #include "common.hpp"
 #include "internal.hpp"
+#include "lttb_core.hpp"
 
 namespace tsds {
-
-__device__ inline int64_t src_of(const LttbParams &p, int64_t j) { return p.sel ? p.sel[j] : j; }
-
-__device__ inline bool int_coord_x(const LttbParams &p) {
-  return p.x_dtype == TS_NONE || p.x_dtype == TS_I32 || p.x_dtype == TS_I64 || p.x_dtype == TS_U32 ||
-         p.x_dtype == TS_U64;
-}
-__device__ inline bool int_coord_y(const LttbParams &p) {
-  return p.y_dtype != TS_F16 && p.y_dtype != TS_F32 && p.y_dtype != TS_F64;
-}
-
-// Exact value of an integer element as a 128-bit integer.
-__device__ inline __int128 int_val(const void *a, int dt, int64_t s) {
-  switch (dt) {
-    case TS_I8: return ((const int8_t *)a)[s];
-    case TS_I16: return ((const int16_t *)a)[s];
-    case TS_I32: return ((const int32_t *)a)[s];
-    case TS_I64: return ((const int64_t *)a)[s];
-    case TS_U8: return ((const uint8_t *)a)[s];
-    case TS_U16: return ((const uint16_t *)a)[s];
-    case TS_U32: return ((const uint32_t *)a)[s];
-    case TS_U64: return (__int128)((const uint64_t *)a)[s];
-  }
-  return 0;
-}
-
-// Element widened to double: exact for <= 32-bit integers and floats, round
-// to nearest for 64-bit integers.
-__device__ inline double dbl_val(const void *a, int dt, int64_t s) {
-  switch (dt) {
-    case TS_I8: return (double)((const int8_t *)a)[s];
-    case TS_I16: return (double)((const int16_t *)a)[s];
-    case TS_I32: return (double)((const int32_t *)a)[s];
-    case TS_I64: return (double)((const int64_t *)a)[s];
-    case TS_U8: return (double)((const uint8_t *)a)[s];
-    case TS_U16: return (double)((const uint16_t *)a)[s];
-    case TS_U32: return (double)((const uint32_t *)a)[s];
-    case TS_U64: return (double)((const uint64_t *)a)[s];
-    case TS_F16: return (double)(float)__builtin_bit_cast(_Float16, ((const uint16_t *)a)[s]);
-    case TS_F32: return (double)((const float *)a)[s];
-    case TS_F64: return ((const double *)a)[s];
-  }
-  return 0.0;
-}
-
-__device__ inline double X_of(const LttbParams &p, int64_t j) {
-  int64_t s = src_of(p, j);
-  return p.x_dtype == TS_NONE ? (double)s : dbl_val(p.x, p.x_dtype, s);
-}
-__device__ inline double Y_of(const LttbParams &p, int64_t j) { return dbl_val(p.y, p.y_dtype, src_of(p, j)); }
-
-// Round a 128-bit integer to the nearest double (ties to even).  The top 64
-// significant bits are kept with every discarded bit folded into the lowest
-// kept bit (round-to-odd), which a single correctly rounded 64 -> 53 bit
-// conversion then finishes without double rounding.
-__device__ inline double i128_to_double(__int128 v) {
-  bool neg = v < 0;
-  unsigned __int128 u = neg ? (unsigned __int128)(-v) : (unsigned __int128)v;
-  uint64_t hi = (uint64_t)(u >> 64), lo = (uint64_t)u;
-  double r;
-  if (hi == 0) {
-    r = (double)lo;
-  } else {
-    int sh = 64 - __builtin_clzll(hi);  // bits of hi in use, 1..64
-    uint64_t top = (sh == 64) ? hi : ((hi << (64 - sh)) | (lo >> sh));
-    uint64_t rest = (sh == 64) ? lo : (lo << (64 - sh));
-    if (rest) top |= 1;
-    r = __builtin_ldexp((double)top, sh);
-  }
-  return neg ? -r : r;
-}
-
-// Mean of X (which == 0) or Y over points [lo, hi), in index order.
-__device__ double coord_mean(const LttbParams &p, int which, int64_t lo, int64_t hi) {
-  const double cnt = (double)(hi - lo);
-  if (which == 0 && p.x_dtype == TS_NONE) {
-    __int128 s = 0;
-    for (int64_t j = lo; j < hi; j++) s += src_of(p, j);
-    return i128_to_double(s) / cnt;
-  }
-  const void *a = which == 0 ? p.x : p.y;
-  const int dt = which == 0 ? p.x_dtype : p.y_dtype;
-  if (which == 0 ? int_coord_x(p) : int_coord_y(p)) {
-    __int128 s = 0;
-    for (int64_t j = lo; j < hi; j++) s += int_val(a, dt, src_of(p, j));
-    return i128_to_double(s) / cnt;
-  }
-  double s = 0.0;
-  for (int64_t j = lo; j < hi; j++) s += dbl_val(a, dt, src_of(p, j));
-  return s / cnt;
-}
-
-// (the host guarantees m * nb < 2^63, so the products fit in 64 bits)
-__device__ inline int64_t bucket_start(int64_t k, int64_t m, int64_t nb) {
-  return 1 + (int64_t)(((uint64_t)k * (uint64_t)(m - 2)) / (uint64_t)nb);
-}
-
-// Bucket holding interior point j (1 <= j <= m-2).
-__device__ inline int64_t bucket_of(int64_t j, int64_t m, int64_t nb) {
-  int64_t k = (int64_t)(((uint64_t)j * (uint64_t)nb + (uint64_t)(m - 2) - 1) / (uint64_t)(m - 2)) - 1;
-  if (k < 0) k = 0;
-  if (k > nb - 1) k = nb - 1;
-  while (k + 1 < nb && bucket_start(k + 1, m, nb) <= j) k++;
-  while (k > 0 && bucket_start(k, m, nb) > j) k--;
-  return k;
-}
-
-__device__ inline double area2(double XA, double YA, double Xb, double Yb, double Cx, double Cy) {
-  return __builtin_fabs((XA - Cx) * (Yb - YA) - (XA - Xb) * (Cy - YA));
-}
-
-__device__ inline int64_t points_m(const LttbParams &p) { return p.m >= 0 ? p.m : *p.m_dev; }
 
 // ---------------------------------------------------------------- centres
 
@@ -170,24 +59,6 @@ hipError_t launch_lttb_centres(const LttbParams &p, hipStream_t st) {
 
 // ---------------------------------------------------------------- small
 
-// First point of bucket k (points [lo, hi)) with the largest area against
-// anchor A and centre k.
-__device__ int64_t best_in_bucket(const LttbParams &p, int64_t lo, int64_t hi, double XA, double YA, double Cx,
-                                  double Cy) {
-  double best = -1.0;
-  int64_t arg = lo;
-  for (int64_t b = lo; b < hi; b++) {
-    double a = area2(XA, YA, X_of(p, b), Y_of(p, b), Cx, Cy);
-    if (a > best) { best = a; arg = b; }
-  }
-  return arg;
-}
-
-__device__ void copy_all(const LttbParams &p, int64_t m) {
-  for (int64_t j = threadIdx.x; j < m; j += blockDim.x) p.out[j] = src_of(p, j);
-  if (threadIdx.x == 0) *p.out_count = m;
-}
-
 // next[] and jump[] live in LDS when `lds_ok`, else in global workspace.
 __global__ __launch_bounds__(1024) void k_lttb_small(LttbParams p, int32_t group, int lds_ok) {
   extern __shared__ int32_t smem[];
@@ -196,72 +67,11 @@ __global__ __launch_bounds__(1024) void k_lttb_small(LttbParams p, int32_t group
     copy_all(p, m);
     return;
   }
-  const int64_t nb = p.n_out - 2;
-  int32_t *next = lds_ok ? smem : p.next;
-  int32_t *jump = lds_ok ? smem + p.m_max : p.next + p.m_max;
-  int32_t *entry = p.entry;
-  const int64_t G = (nb + group - 1) / group;
-
-  // 1. transition map: next[a] = pick in bucket k+1 when the pick in bucket k
-  //    is a (a = 0 stands for the first point, before bucket 0).
-  for (int64_t a = threadIdx.x; a < m - 1; a += blockDim.x) {
-    const int64_t k = a == 0 ? -1 : bucket_of(a, m, nb);
-    if (k == nb - 1) {
-      next[a] = (int32_t)(m - 1);
-      continue;
-    }
-    const int64_t lo = bucket_start(k + 1, m, nb), hi = bucket_start(k + 2, m, nb);
-    next[a] = (int32_t)best_in_bucket(p, lo, hi, X_of(p, a), Y_of(p, a), p.cx[k + 1], p.cy[k + 1]);
-  }
-  __syncthreads();
-
-  // 2. group exits: for every possible entry a of group g (the first point
-  //    for g = 0, else any point of bucket g*group - 1), follow next[] over
-  //    the group's buckets.  (group, entry) pairs are spread over threads.
-  const int64_t P = (m - 2 + nb - 1) / nb + 1;  // >= largest bucket
-  for (int64_t idx = threadIdx.x; idx < G * P; idx += blockDim.x) {
-    const int64_t g = idx / P, off = idx % P;
-    const int64_t lo = g == 0 ? 0 : bucket_start(g * group - 1, m, nb);
-    const int64_t hi = g == 0 ? 1 : bucket_start(g * group, m, nb);
-    const int64_t a = lo + off;
-    if (a >= hi) continue;
-    const int64_t k1 = (g + 1) * group < nb ? (g + 1) * group : nb;
-    int32_t v = (int32_t)a;
-    for (int64_t s = g * group; s < k1; s++) v = next[v];
-    jump[a] = v;
-  }
-  __syncthreads();
-
-  // 3. chain over groups.
-  if (threadIdx.x == 0) {
-    int32_t v = 0;
-    for (int64_t g = 0; g < G; g++) {
-      entry[g] = v;
-      v = jump[v];
-    }
-  }
-  __syncthreads();
-
-  // 4. group interiors in parallel.
-  for (int64_t g = threadIdx.x; g < G; g += blockDim.x) {
-    int32_t v = entry[g];
-    const int64_t k1 = (g + 1) * group < nb ? (g + 1) * group : nb;
-    for (int64_t k = g * group; k < k1; k++) {
-      v = next[v];
-      p.out[k + 1] = src_of(p, v);
-    }
-  }
-  if (threadIdx.x == 0) {
-    p.out[0] = src_of(p, 0);
-    p.out[p.n_out - 1] = src_of(p, m - 1);
-    *p.out_count = p.n_out;
-  }
+  lttb_small_walk(p, m, lds_ok ? smem : p.next, lds_ok ? smem + p.m_max : p.next + p.m_max, group);
 }
 
 hipError_t launch_lttb_small(const LttbParams &p, hipStream_t st) {
-  const int64_t nb = p.n_out - 2;
-  int32_t group = 1;
-  while ((int64_t)group * group * 2 < nb) group *= 2;
+  const int32_t group = lttb_group_len(p.n_out - 2);
   const size_t lds = (size_t)p.m_max * 2 * sizeof(int32_t);
   const int lds_ok = lds <= 128 * 1024;
   k_lttb_small<<<dim3(1), dim3(1024), lds_ok ? lds : 0, st>>>(p, group, lds_ok);
@@ -270,8 +80,7 @@ hipError_t launch_lttb_small(const LttbParams &p, hipStream_t st) {
 
 size_t lttb_group_count(int64_t n_out) {
   const int64_t nb = n_out - 2;
-  int64_t group = 1;
-  while (group * group * 2 < nb) group *= 2;
+  const int64_t group = lttb_group_len(nb);
   return (size_t)((nb + group - 1) / group);
 }
 

@@ -25,107 +25,19 @@
 
 #include "common.hpp"
 #include "internal.hpp"
+#include "scan_core.hpp"
 
 namespace tsds {
 
-typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-
 // ------------------------------------------------------------------ edges
 
-template <typename X> struct XKey;
-template <> struct XKey<int32_t> { using K = int64_t; };
-template <> struct XKey<int64_t> { using K = int64_t; };
-template <> struct XKey<uint32_t> { using K = uint64_t; };
-template <> struct XKey<uint64_t> { using K = uint64_t; };
-
-// Integer edge value E_b = x0 + ceil(b * R / nb) with R = x_last - x0 >= 0,
-// exact although b*R may need 128 bits: with R = q*nb + r,
-// b*R/nb = b*q + b*r/nb, and b*r < nb^2 < 2^64 (the host keeps nb < 2^32).
-__device__ inline uint64_t ceil_mul_div(uint64_t b, uint64_t R, uint64_t nb) {
-  uint64_t q = R / nb, r = R % nb;
-  uint64_t br = b * r;
-  uint64_t t = br / nb;
-  return b * q + t + (t * nb == br ? 0 : 1);
-}
-
-// Wavefront-cooperative lower bound: the first index i in [0, n) with
-// x[i] >= v (n if none).  Each round probes 64 evenly spaced positions.
-template <typename X, typename K>
-__device__ int64_t wave_lower_bound(const X *x, int64_t n, K v, int lane) {
-  int64_t lo = 0, hi = n;  // answer in [lo, hi]; x[lo-1] < v, x[hi] >= v
-  while (hi > lo) {
-    int64_t span = hi - lo;
-    int64_t step = (span + 63) / 64;
-    int64_t q = lo + (int64_t)lane * step;
-    bool less = q < hi && (K)x[q] < v;
-    int cnt = __builtin_popcountll(ballot(less));  // lanes 0..cnt-1 are below v
-    if (cnt == 0) {
-      hi = lo;
-    } else {
-      int64_t nlo = lo + (int64_t)(cnt - 1) * step + 1;
-      int64_t nhi = lo + (int64_t)cnt * step;
-      lo = nlo;
-      hi = nhi < hi ? nhi : hi;
-    }
-  }
-  return lo;
-}
-
 template <typename X>
-__global__ __launch_bounds__(256) void k_edges_int(const X *x, int64_t n, int64_t nb, int64_t *edges) {
-  using K = typename XKey<X>::K;
+__global__ __launch_bounds__(256) void k_edges_x(const X *x, int64_t n, int64_t nb, int64_t *edges) {
   const int lane = lane_id();
   const int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (b > nb) return;
-  if (b == nb) {
-    if (lane == 0) edges[nb] = n;
-    return;
-  }
-  if (b == 0) {
-    if (lane == 0) edges[0] = 0;
-    return;
-  }
-  K x0 = (K)x[0], xl = (K)x[n - 1];
-  uint64_t R = (uint64_t)xl - (uint64_t)x0;  // exact modulo 2^64, x sorted
-  K E = (K)((uint64_t)x0 + ceil_mul_div((uint64_t)b, R, (uint64_t)nb));
-  int64_t s = wave_lower_bound<X, K>(x, n, E, lane);
+  const int64_t s = edge_start<X>(x, n, nb, b, lane);
   if (lane == 0) edges[b] = s;
-}
-
-template <typename X>
-__global__ __launch_bounds__(256) void k_edges_float(const X *x, int64_t n, int64_t nb, int64_t *edges) {
-  const int lane = lane_id();
-  const int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (b > nb) return;
-  if (b == nb) {
-    if (lane == 0) edges[nb] = n;
-    return;
-  }
-  if (b == 0) {
-    if (lane == 0) edges[0] = 0;
-    return;
-  }
-  double x0 = (double)x[0], R = (double)x[n - 1] - x0;
-  // E_b = x0 + (b * R) / nb, each operation rounded to nearest (the unit is
-  // built with -ffp-contract=off, so no FMA joins the product and the sum).
-  double E = x0 + ((double)b * R) / (double)nb;
-  // lower bound on the widened values
-  int64_t lo = 0, hi = n;
-  while (hi > lo) {
-    int64_t step = (hi - lo + 63) / 64;
-    int64_t q = lo + (int64_t)lane * step;
-    bool less = q < hi && (double)x[q] < E;
-    int cnt = __builtin_popcountll(ballot(less));
-    if (cnt == 0) {
-      hi = lo;
-    } else {
-      int64_t nlo = lo + (int64_t)(cnt - 1) * step + 1;
-      int64_t nhi = lo + (int64_t)cnt * step;
-      lo = nlo;
-      hi = nhi < hi ? nhi : hi;
-    }
-  }
-  if (lane == 0) edges[b] = lo;
 }
 
 __global__ void k_edges_nox(int64_t n, int64_t nb, int64_t *edges) {
@@ -145,438 +57,15 @@ hipError_t launch_edges_nox(int64_t n, int64_t nb, int64_t *edges, hipStream_t s
 hipError_t launch_edges_x(const void *x, int xdt, int64_t n, int64_t nb, int64_t *edges, hipStream_t st) {
   dim3 grid((unsigned)((nb + 1 + 3) / 4)), block(256);
   switch (xdt) {
-    case TS_I32: k_edges_int<int32_t><<<grid, block, 0, st>>>((const int32_t *)x, n, nb, edges); break;
-    case TS_I64: k_edges_int<int64_t><<<grid, block, 0, st>>>((const int64_t *)x, n, nb, edges); break;
-    case TS_U32: k_edges_int<uint32_t><<<grid, block, 0, st>>>((const uint32_t *)x, n, nb, edges); break;
-    case TS_U64: k_edges_int<uint64_t><<<grid, block, 0, st>>>((const uint64_t *)x, n, nb, edges); break;
-    case TS_F32: k_edges_float<float><<<grid, block, 0, st>>>((const float *)x, n, nb, edges); break;
-    case TS_F64: k_edges_float<double><<<grid, block, 0, st>>>((const double *)x, n, nb, edges); break;
+    case TS_I32: k_edges_x<int32_t><<<grid, block, 0, st>>>((const int32_t *)x, n, nb, edges); break;
+    case TS_I64: k_edges_x<int64_t><<<grid, block, 0, st>>>((const int64_t *)x, n, nb, edges); break;
+    case TS_U32: k_edges_x<uint32_t><<<grid, block, 0, st>>>((const uint32_t *)x, n, nb, edges); break;
+    case TS_U64: k_edges_x<uint64_t><<<grid, block, 0, st>>>((const uint64_t *)x, n, nb, edges); break;
+    case TS_F32: k_edges_x<float><<<grid, block, 0, st>>>((const float *)x, n, nb, edges); break;
+    case TS_F64: k_edges_x<double><<<grid, block, 0, st>>>((const double *)x, n, nb, edges); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
-}
-
-// ------------------------------------------------------------------ scan
-
-// Start of bin b (b <= nb); b >= nb gives the end of the last bin.
-__device__ inline int64_t edge_at(const int64_t *edges, int64_t n, int64_t nb, int64_t b) {
-  if (b >= nb) return edges ? edges[nb] : n;
-  if (edges) return edges[b];
-  uint64_t num = (uint64_t)b * (uint64_t)(n - 1);
-  return (int64_t)((num + (uint64_t)nb - 1) / (uint64_t)nb);
-}
-
-// First bin whose range can intersect [c0, ...): the last b with start <= c0.
-__device__ int64_t first_bin(const int64_t *edges, int64_t n, int64_t nb, int64_t c0, int lane) {
-  if (!edges) {
-    if (n <= 1) return 0;
-    uint64_t q = (uint64_t)c0 * (uint64_t)nb / (uint64_t)(n - 1);
-    return q < (uint64_t)nb ? (int64_t)q : nb - 1;
-  }
-  if (edges[0] > c0) return 0;
-  int64_t lo = 0, hi = nb;  // edges[lo] <= c0; the answer is < hi
-  while (hi - lo > 1) {
-    int64_t step = (hi - lo + 63) / 64;
-    int64_t q = lo + (int64_t)lane * step;
-    bool le = q < hi && edges[q] <= c0;
-    int cnt = __builtin_popcountll(ballot(le));
-    int64_t nlo = lo + (int64_t)(cnt - 1) * step;
-    int64_t nhi = lo + (int64_t)cnt * step;
-    lo = nlo;
-    hi = nhi < hi ? nhi : hi;
-  }
-  return lo;
-}
-
-template <typename T>
-__device__ inline typename Elem<T>::C extract(const u32x4 &d, int j) {
-  constexpr int VEC = 16 / (int)sizeof(T);
-  T tmp[VEC];
-  __builtin_memcpy(tmp, &d, 16);
-  return Elem<T>::load(&tmp[j]);
-}
-
-template <typename T>
-__device__ inline void write_result(const ScanParams &p, int64_t c, int64_t bin, bool before, bool after,
-                                    typename Elem<T>::C vmn, int64_t imn, typename Elem<T>::C vmx,
-                                    int64_t imx) {
-  if (!before && !after) {
-    p.binres[2 * bin] = imn;
-    p.binres[2 * bin + 1] = imx;
-  } else {
-    Partial q;
-    q.kmin = Elem<T>::key(vmn);
-    q.imin = imn;
-    q.kmax = Elem<T>::key(vmx);
-    q.imax = imx;
-    (before ? p.partL : p.partR)[c] = q;
-  }
-}
-
-// ---- per-vector reductions and searches ------------------------------------
-//
-// A tile is U 16-byte vectors per lane; vector u of lane l holds tile
-// positions (u*64 + l)*VEC + j, j < VEC, so tile order is (u, lane, j).
-// VecOps<T>::minmax reduces one vector to its minimum and maximum value;
-// narrow types use packed 16-bit min/max (two elements per instruction),
-// bytes being spread into two 16-bit pairs first (signed bytes biased by 0x80
-// so that unsigned order is numeric order).  VecOps<T>::first returns the
-// first j whose element equals a value (VEC if none); bytes and halves test
-// four or two elements per instruction with the zero-lane bit trick.
-
-typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
-typedef short i16x2 __attribute__((ext_vector_type(2)));
-typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
-
-template <typename V>
-__device__ inline V as2(uint32_t w) { return __builtin_bit_cast(V, w); }
-
-// Lowest 8-bit (B = 8) or 16-bit (B = 16) lane of t that is zero, or -1.
-template <int B>
-__device__ inline int first_zero_lane(uint32_t t) {
-  constexpr uint32_t ONES = B == 8 ? 0x01010101u : 0x00010001u;
-  constexpr uint32_t HIGH = B == 8 ? 0x80808080u : 0x80008000u;
-  const uint32_t z = (t - ONES) & ~t & HIGH;  // lowest set bit marks the lowest zero lane
-  return z ? (int)(__builtin_ctz(z) / B) : -1;
-}
-
-template <typename T> struct VecOps {
-  using C = typename Elem<T>::C;
-  static constexpr int VEC = 16 / (int)sizeof(T);
-  static __device__ inline void minmax(const u32x4 &d, C &mn, C &mx) {
-    mn = extract<T>(d, 0);
-    mx = mn;
-#pragma unroll
-    for (int j = 1; j < VEC; j++) {
-      const C v = extract<T>(d, j);
-      mn = vmin(mn, v);
-      mx = vmax(mx, v);
-    }
-  }
-  static __device__ inline int first(const u32x4 &d, C target) {
-    int r = VEC;
-#pragma unroll
-    for (int j = VEC - 1; j >= 0; j--)
-      if (extract<T>(d, j) == target) r = j;
-    return r;
-  }
-};
-
-template <typename V>
-__device__ inline void pk_vec_minmax(const u32x4 &d, V &a, V &b) {
-  a = as2<V>(d.x);
-  b = a;
-#pragma unroll
-  for (int c = 1; c < 4; c++) {
-    const V v = as2<V>(d[c]);
-    a = __builtin_elementwise_min(a, v);
-    b = __builtin_elementwise_max(b, v);
-  }
-}
-
-template <typename T, uint32_t SIGNMASK>
-__device__ inline int first16(const u32x4 &d, uint32_t pattern16) {
-  const uint32_t pat = pattern16 | (pattern16 << 16);
-#pragma unroll
-  for (int c = 0; c < 4; c++) {
-    const int k = first_zero_lane<16>((d[c] & ~SIGNMASK) ^ pat);
-    if (k >= 0) return 2 * c + k;
-  }
-  return 8;
-}
-
-template <> struct VecOps<uint16_t> {
-  static __device__ inline void minmax(const u32x4 &d, uint32_t &mn, uint32_t &mx) {
-    u16x2 a, b;
-    pk_vec_minmax(d, a, b);
-    mn = a.x < a.y ? a.x : a.y;
-    mx = b.x < b.y ? b.y : b.x;
-  }
-  static __device__ inline int first(const u32x4 &d, uint32_t t) { return first16<uint16_t, 0u>(d, t & 0xffffu); }
-};
-template <> struct VecOps<int16_t> {
-  static __device__ inline void minmax(const u32x4 &d, int32_t &mn, int32_t &mx) {
-    i16x2 a, b;
-    pk_vec_minmax(d, a, b);
-    mn = a.x < a.y ? a.x : a.y;
-    mx = b.x < b.y ? b.y : b.x;
-  }
-  static __device__ inline int first(const u32x4 &d, int32_t t) {
-    return first16<int16_t, 0u>(d, (uint32_t)t & 0xffffu);
-  }
-};
-template <> struct VecOps<half_t> {
-  static __device__ inline void minmax(const u32x4 &d, _Float16 &mn, _Float16 &mx) {
-    f16x2 a, b;
-    pk_vec_minmax(d, a, b);
-    mn = vmin(a.x, a.y);
-    mx = vmax(b.x, b.y);
-  }
-  // Equal values have equal bits except for the two zeros: a zero target
-  // compares magnitudes only.
-  static __device__ inline int first(const u32x4 &d, _Float16 t) {
-    const uint32_t bits = __builtin_bit_cast(uint16_t, t);
-    if ((bits & 0x7fffu) == 0) return first16<half_t, 0x80008000u>(d, 0u);
-    return first16<half_t, 0u>(d, bits);
-  }
-};
-
-// Bytes: w = [b0 b1 b2 b3] -> (b0, b2) and (b1, b3) as 16-bit pairs.
-template <uint32_t BIAS>
-__device__ inline void byte_vec_minmax(const u32x4 &d, uint32_t &mn, uint32_t &mx) {
-  u16x2 a, b;
-#pragma unroll
-  for (int c = 0; c < 4; c++) {
-    const uint32_t w = d[c] ^ BIAS;
-    const u16x2 lo = as2<u16x2>(w & 0x00ff00ffu), hi = as2<u16x2>((w >> 8) & 0x00ff00ffu);
-    const u16x2 m0 = __builtin_elementwise_min(lo, hi), m1 = __builtin_elementwise_max(lo, hi);
-    a = c == 0 ? m0 : __builtin_elementwise_min(a, m0);
-    b = c == 0 ? m1 : __builtin_elementwise_max(b, m1);
-  }
-  mn = a.x < a.y ? a.x : a.y;
-  mx = b.x < b.y ? b.y : b.x;
-}
-__device__ inline int first8(const u32x4 &d, uint32_t raw_byte) {
-  const uint32_t pat = raw_byte * 0x01010101u;
-#pragma unroll
-  for (int c = 0; c < 4; c++) {
-    const int k = first_zero_lane<8>(d[c] ^ pat);
-    if (k >= 0) return 4 * c + k;
-  }
-  return 16;
-}
-template <> struct VecOps<uint8_t> {
-  static __device__ inline void minmax(const u32x4 &d, uint32_t &mn, uint32_t &mx) {
-    byte_vec_minmax<0u>(d, mn, mx);
-  }
-  static __device__ inline int first(const u32x4 &d, uint32_t t) { return first8(d, t & 0xffu); }
-};
-template <> struct VecOps<int8_t> {
-  static __device__ inline void minmax(const u32x4 &d, int32_t &mn, int32_t &mx) {
-    uint32_t a, b;
-    byte_vec_minmax<0x80808080u>(d, a, b);
-    mn = (int32_t)a - 128;
-    mx = (int32_t)b - 128;
-  }
-  static __device__ inline int first(const u32x4 &d, int32_t t) { return first8(d, (uint32_t)t & 0xffu); }
-};
-
-// Masked versions (segment ends): positions outside [rlo, rhi) are ignored.
-template <typename T>
-__device__ inline void vec_minmax_masked(const u32x4 &d, uint32_t q0, uint32_t rlo, uint32_t rhi,
-                                         typename Elem<T>::C &mn, typename Elem<T>::C &mx) {
-  using E = Elem<T>;
-  constexpr int VEC = 16 / (int)sizeof(T);
-  mn = E::highest();
-  mx = E::lowest();
-#pragma unroll
-  for (int j = 0; j < VEC; j++) {
-    const bool ok = q0 + j >= rlo && q0 + j < rhi;
-    const typename E::C v = extract<T>(d, j);
-    mn = vmin(mn, ok ? v : E::highest());
-    mx = vmax(mx, ok ? v : E::lowest());
-  }
-}
-template <typename T>
-__device__ inline int vec_first_masked(const u32x4 &d, typename Elem<T>::C target, uint32_t q0, uint32_t rlo,
-                                       uint32_t rhi) {
-  constexpr int VEC = 16 / (int)sizeof(T);
-  int r = VEC;
-#pragma unroll
-  for (int j = VEC - 1; j >= 0; j--)
-    if (q0 + j >= rlo && q0 + j < rhi && extract<T>(d, j) == target) r = j;
-  return r;
-}
-
-// Running result of one bin segment (wave-uniform).
-template <typename C> struct SegState {
-  C vmn, vmx;
-  int64_t imn, imx;
-  bool has;
-};
-
-// Load tile vt (vectors vt + u*64 + lane); vectors outside [vlo, vhi) are not
-// read (zero).
-template <int U>
-__device__ inline void load_tile(const u32x4 *__restrict__ base, int64_t vt, int64_t vlo, int64_t vhi, int lane,
-                                 u32x4 (&d)[U]) {
-  if (vt >= vlo && vt + (int64_t)kWave * U <= vhi) {
-#pragma unroll
-    for (int u = 0; u < U; u++) d[u] = __builtin_nontemporal_load(base + vt + u * kWave + lane);
-  } else {
-#pragma unroll
-    for (int u = 0; u < U; u++) {
-      const int64_t v = vt + u * kWave + lane;
-      d[u] = (v >= vlo && v < vhi) ? __builtin_nontemporal_load(base + v) : u32x4{0u, 0u, 0u, 0u};
-    }
-  }
-}
-
-// Tile position of the first element equal to `target` (which some valid
-// element holds): the first vector index u whose per-vector extreme equals
-// the target on some lane, the lowest such lane, then the first j in that
-// lane's vector.  All branches are wave-uniform.
-template <typename T, int U>
-__device__ inline uint32_t locate(const u32x4 (&d)[U], const typename Elem<T>::C (&ve)[U], typename Elem<T>::C target,
-                                  bool full, uint32_t rlo, uint32_t rhi, int lane) {
-  constexpr int VEC = 16 / (int)sizeof(T);
-  uint32_t pos = 0;
-  bool found = false;
-#pragma unroll
-  for (int u = 0; u < U; u++) {
-    if (!found) {
-      const uint32_t q0 = (uint32_t)((u * kWave + lane) * VEC);
-      const bool hv = full || (q0 + VEC > rlo && q0 < rhi);
-      const uint64_t m = ballot(hv && ve[u] == target);
-      if (m) {
-        const int l = __builtin_ctzll(m);
-        const int jl = full ? VecOps<T>::first(d[u], target) : vec_first_masked<T>(d[u], target, q0, rlo, rhi);
-        const int j = __builtin_amdgcn_readlane(jl, l);
-        pos = (uint32_t)((u * kWave + l) * VEC + j);
-        found = true;
-      }
-    }
-  }
-  return pos;
-}
-
-// Fold one tile into the running result of segment [lo, hi).  Values are
-// reduced per vector and per lane, DPP gives the wavefront's extremes, and a
-// tile is searched for the position of its extreme only when that extreme
-// strictly beats the running one: equal values in later tiles never replace
-// an earlier index.
-template <typename T, int U>
-__device__ inline void fold_tile(const u32x4 (&d)[U], int64_t vt, int64_t shift, int64_t lo, int64_t hi, int lane,
-                                 SegState<typename Elem<T>::C> &st) {
-  using E = Elem<T>;
-  using C = typename E::C;
-  constexpr int VEC = 16 / (int)sizeof(T);
-  constexpr int64_t TE = (int64_t)kWave * U * VEC;  // elements per tile
-  const int64_t g0 = vt * VEC - shift;               // index of tile position 0
-  const bool full = g0 >= lo && g0 + TE <= hi;
-  const uint32_t rlo = (uint32_t)(lo > g0 ? lo - g0 : 0);
-  const uint32_t rhi = (uint32_t)(hi < g0 + TE ? hi - g0 : TE);
-  C vm[U], vx[U];
-  if (full) {
-#pragma unroll
-    for (int u = 0; u < U; u++) VecOps<T>::minmax(d[u], vm[u], vx[u]);
-  } else {
-#pragma unroll
-    for (int u = 0; u < U; u++)
-      vec_minmax_masked<T>(d[u], (uint32_t)((u * kWave + lane) * VEC), rlo, rhi, vm[u], vx[u]);
-  }
-  C tmn = vm[0], tmx = vx[0];
-#pragma unroll
-  for (int u = 1; u < U; u++) {
-    tmn = vmin(tmn, vm[u]);
-    tmx = vmax(tmx, vx[u]);
-  }
-  const C wmn = wave_min(tmn), wmx = wave_max(tmx);
-  if (!st.has || wmn < st.vmn) {
-    st.imn = g0 + locate<T, U>(d, vm, wmn, full, rlo, rhi, lane);
-    st.vmn = wmn;
-  }
-  if (!st.has || st.vmx < wmx) {
-    st.imx = g0 + locate<T, U>(d, vx, wmx, full, rlo, rhi, lane);
-    st.vmx = wmx;
-  }
-  st.has = true;
-}
-
-// Whole-wavefront argmin/argmax of y[lo, hi) (lo < hi, wave-uniform), tile by
-// tile with NB tiles in flight.  The first `npre` tiles may already be in buf
-// (the chunk prefetch).
-template <typename T, int U, int NB>
-__device__ void wave_segment(const u32x4 *__restrict__ base, int64_t shift, int64_t lo, int64_t hi, int lane,
-                             u32x4 (&buf)[NB][U], int npre, SegState<typename Elem<T>::C> &st) {
-  constexpr int VEC = 16 / (int)sizeof(T);
-  constexpr int64_t TV = (int64_t)kWave * U;  // vectors per tile
-  const int64_t v_lo = (lo + shift) / VEC;
-  const int64_t v_hi = (hi + shift + VEC - 1) / VEC;
-  const int64_t ntiles = (v_hi - v_lo + TV - 1) / TV;
-  st.has = false;
-#pragma unroll
-  for (int k = 0; k < NB; k++)
-    if (k >= npre && k < ntiles) load_tile<U>(base, v_lo + k * TV, v_lo, v_hi, lane, buf[k]);
-  for (int64_t t = 0; t < ntiles; t += NB) {
-#pragma unroll
-    for (int k = 0; k < NB; k++) {
-      if (t + k < ntiles) {
-        const int64_t vt = v_lo + (t + k) * TV;
-        fold_tile<T, U>(buf[k], vt, shift, lo, hi, lane, st);
-        if (t + k + NB < ntiles) load_tile<U>(base, vt + NB * TV, v_lo, v_hi, lane, buf[k]);
-      }
-    }
-  }
-}
-
-template <typename T, int U, int NB>
-__global__ __launch_bounds__(256) void k_scan(ScanParams p) {
-  using E = Elem<T>;
-  using C = typename E::C;
-  constexpr int VEC = 16 / (int)sizeof(T);
-  constexpr int64_t TV = (int64_t)kWave * U;
-  const int lane = lane_id();
-  const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (c >= p.nchunks) return;
-  const T *__restrict__ y = (const T *)p.y;
-  const u32x4 *__restrict__ base = (const u32x4 *)(y - p.shift);
-  int64_t c0 = c * p.chunk - p.shift;
-  if (c0 < 0) c0 = 0;
-  int64_t c1 = (c + 1) * p.chunk - p.shift;
-  if (c1 > p.n) c1 = p.n;
-  if (p.edges) {  // caller bins may not cover the whole series
-    const int64_t e0 = p.edges[0], en = p.edges[p.nb];
-    if (c0 < e0) c0 = e0;
-    if (c1 > en) c1 = en;
-  }
-  if (c0 >= c1) return;
-
-  // Prefetch the chunk's first tiles: they do not depend on the bins, so
-  // their latency overlaps the bin search below.  A big segment starting at
-  // the chunk start (the usual case) consumes them.
-  const int64_t vc0 = (c0 + p.shift) / VEC, vc1 = (c1 + p.shift + VEC - 1) / VEC;
-  u32x4 buf[NB][U];
-#pragma unroll
-  for (int k = 0; k < NB; k++) load_tile<U>(base, vc0 + k * TV, vc0, vc1, lane, buf[k]);
-  int npre = NB;
-
-  int64_t b = first_bin(p.edges, p.n, p.nb, c0, lane);
-  for (;;) {
-    const int64_t bb = b + lane;
-    const bool inb = bb < p.nb;
-    const int64_t s = edge_at(p.edges, p.n, p.nb, bb);
-    const int64_t e = edge_at(p.edges, p.n, p.nb, bb + 1);
-    const int64_t lo = s > c0 ? s : c0;
-    const int64_t hi = e < c1 ? e : c1;
-    const bool valid = inb && lo < hi;
-    const bool before = s < c0, after = e > c1;
-    const bool small = valid && (hi - lo) < p.small;
-    if (small) {
-      C vmn = E::load(y + lo), vmx = vmn;
-      int64_t imn = lo, imx = lo;
-      for (int64_t i = lo + 1; i < hi; i++) {
-        C v = E::load(y + i);
-        if (v < vmn) { vmn = v; imn = i; }
-        if (vmx < v) { vmx = v; imx = i; }
-      }
-      write_result<T>(p, c, bb, before, after, vmn, imn, vmx, imx);
-    }
-    uint64_t big = ballot(valid && !small);
-    while (big) {
-      const int k = __builtin_ctzll(big);
-      big &= big - 1;
-      const int64_t slo = readlane(lo, k), shi = readlane(hi, k);
-      SegState<C> st;
-      wave_segment<T, U, NB>(base, p.shift, slo, shi, lane, buf, slo == c0 ? npre : 0, st);
-      npre = 0;
-      const bool sb = readlane(s, k) < c0, sa = readlane(e, k) > c1;
-      if (lane == 0) write_result<T>(p, c, b + k, sb, sa, st.vmn, st.imn, st.vmx, st.imx);
-    }
-    const int64_t e63 = readlane(e, 63);
-    if (e63 >= c1 || b + kWave >= p.nb) break;
-    b += kWave;
-  }
 }
 
 // Tile shapes: 16-byte vectors per lane per tile x tiles in flight.
@@ -611,36 +100,6 @@ hipError_t launch_scan(int ydt, const ScanParams &p, hipStream_t st) {
 
 // ------------------------------------------------------------------ merge
 
-// Per bin: the final (argmin, argmax), merged lexicographically from the
-// partials of every chunk the bin touches when it straddles chunks.
-__device__ void merged_bin(const MergeParams &p, int64_t s, int64_t e, int64_t bin, int lane, int64_t &imn,
-                           int64_t &imx) {
-  const int64_t cs = (s + p.shift) / p.chunk, ce = (e - 1 + p.shift) / p.chunk;
-  if (cs == ce) {
-    imn = p.binres[2 * bin];
-    imx = p.binres[2 * bin + 1];
-    return;
-  }
-  uint64_t kmn = ~0ull, kmx = 0;
-  int64_t jmn = INT64_MAX, jmx = INT64_MAX;
-  for (int64_t c = cs + lane; c <= ce; c += kWave) {
-    const Partial q = (c == cs) ? p.partR[c] : p.partL[c];
-    lex_min(kmn, jmn, q.kmin, q.imin);
-    lex_max(kmx, jmx, q.kmax, q.imax);
-  }
-  const uint64_t wkmn = wave_min(kmn), wkmx = wave_max(kmx);
-  imn = wave_min(kmn == wkmn ? jmn : INT64_MAX);
-  imx = wave_min(kmx == wkmx ? jmx : INT64_MAX);
-}
-
-// Bin b clipped to [0, n) (caller edges are not trusted to stay in range).
-__device__ inline void bin_range(const MergeParams &p, int64_t bin, int64_t &s, int64_t &e) {
-  s = edge_at(p.edges, p.n, p.nb, bin);
-  e = edge_at(p.edges, p.n, p.nb, bin + 1);
-  s = s < 0 ? 0 : (s > p.n ? p.n : s);
-  e = e < s ? s : (e > p.n ? p.n : e);
-}
-
 __global__ __launch_bounds__(256) void k_merge(MergeParams p) {
   const int lane = lane_id();
   const int64_t bin = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -653,21 +112,7 @@ __global__ __launch_bounds__(256) void k_merge(MergeParams p) {
   }
   int64_t imn, imx;
   merged_bin(p, s, e, bin, lane, imn, imx);
-  if (lane != 0) return;
-  int64_t v[4];
-  int k = 0;
-  if (p.m4) v[k++] = s;
-  v[k++] = imn;
-  v[k++] = imx;
-  if (p.m4) v[k++] = e - 1;
-  for (int a = 1; a < k; a++)
-    for (int c = a; c > 0 && v[c - 1] > v[c]; c--) {
-      int64_t t = v[c]; v[c] = v[c - 1]; v[c - 1] = t;
-    }
-  int m = 0;
-  for (int a = 0; a < k; a++)
-    if (a == 0 || v[a] != v[a - 1]) p.sel[4 * bin + m++] = v[a];
-  p.cnt[bin] = m;
+  if (lane == 0) p.cnt[bin] = bin_selection(s, e, imn, imx, p.m4, p.sel + 4 * bin);
 }
 
 hipError_t launch_merge(const MergeParams &p, hipStream_t st) {
@@ -696,35 +141,6 @@ hipError_t launch_binres_to_outputs(const MergeParams &p, int64_t *imin, int64_t
 }
 
 // ------------------------------------------------------------------ compact
-
-// Exclusive scan of one int64 per thread over a 1024-thread block.
-__device__ int64_t block_exclusive_scan(int64_t v, int64_t *lds, int64_t &total) {
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  int64_t incl = v;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    int64_t o = __shfl_up(incl, d, 64);
-    if (lane >= d) incl += o;
-  }
-  if (lane == 63) lds[w] = incl;
-  __syncthreads();
-  if (w == 0) {
-    int64_t ws = lane < (int)(blockDim.x >> 6) ? lds[lane] : 0;
-    int64_t wi = ws;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      int64_t o = __shfl_up(wi, d, 64);
-      if (lane >= d) wi += o;
-    }
-    if (lane < (int)(blockDim.x >> 6)) lds[32 + lane] = wi - ws;
-    if (lane == 63) lds[64] = wi;
-  }
-  __syncthreads();
-  total = lds[64];
-  int64_t r = lds[32 + w] + incl - v;
-  __syncthreads();
-  return r;
-}
 
 __global__ __launch_bounds__(1024) void k_compact(CompactParams p) {
   __shared__ int64_t lds[80];
@@ -780,7 +196,7 @@ __global__ void k_window(const X *x, int64_t n, int64_t xa, int64_t xb, int64_t 
     if (std::is_unsigned<K>::value && xb < 0) v = 0;
     else v = (K)xb == (K)(std::numeric_limits<K>::max()) ? (K)xb : (K)((K)xb + 1);
   }
-  int64_t r = wave_lower_bound<X, K>(x, n, v, lane);
+  int64_t r = wave_lower_bound<X, K>(x, 0, n, v, lane);
   if (w == 1 && !(std::is_unsigned<K>::value && xb < 0) && (K)xb == std::numeric_limits<K>::max()) r = n;
   if (lane == 0) range[w] = r;
 }
