@@ -99,6 +99,89 @@ def cpu_baseline(name, x, y, w, budget_s=12.0):
                       f"{med * 1e3:.1f} ms"}, res
 
 
+def bench_batched(seed=3, n_series=512, reps=10):
+    """Batched vs plain on the mixed batch: 512 series, lengths log-uniform in
+    1e4..2e7, dtypes f32/f16/i16/u8, MinMax / M4, n_out 500..4000."""
+    import torch
+    import oracle
+    import paper_2307_05389_amd as tsds
+    import synthetic as S
+    specs = S.batch_specs(n_series, seed=seed)
+    log(f"[bench] batched: generating {n_series} series on the GPU")
+    ys = [S.device_walk_cast(s["n"], s["dtype"], s["seed"]) for s in specs]
+    total_bytes = sum(y.numel() * y.element_size() for y in ys)
+    tasks = [dict(algo=s["algo"], y=y, n_out=s["n_out"]) for s, y in zip(specs, ys)]
+    b = tsds.Batch(tasks)
+    tune = b.autotune()
+    st = torch.cuda.current_stream()
+    b.run(graph=True)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        b.run(graph=True)
+    e1.record(st)
+    torch.cuda.synchronize()
+    t_batch = e0.elapsed_time(e1) / reps
+    batched = [r.clone() for r in b.results()]
+    # plain: one single-series call per task on one stream (own outputs, one
+    # shared workspace), eager and replayed from a torch-captured graph
+    outs = [torch.empty(s["n_out"], dtype=torch.int64, device=y.device) for s, y in zip(specs, ys)]
+    cnts = torch.zeros(len(specs), dtype=torch.int64, device=ys[0].device)
+    need = max(tsds.workspace_bytes(s["algo"], y, s["n_out"]) for s, y in zip(specs, ys))
+    ws = torch.empty(need, dtype=torch.uint8, device=ys[0].device)
+
+    def plain(stream):
+        for i, (s, y) in enumerate(zip(specs, ys)):
+            tsds.downsample_into(s["algo"], y, s["n_out"], outs[i], cnts[i:i + 1], workspace=ws, stream=stream)
+
+    plain(st)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(st)
+    for _ in range(reps):
+        plain(st)
+    e1.record(st)
+    torch.cuda.synchronize()
+    t_plain_eager = e0.elapsed_time(e1) / reps
+    wall_plain = (time.perf_counter() - t0) * 1e3 / reps
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    with torch.cuda.graph(g, stream=side):
+        plain(torch.cuda.current_stream())
+    g.replay()
+    torch.cuda.synchronize()
+    e0.record(st)
+    for _ in range(reps):
+        g.replay()
+    e1.record(st)
+    torch.cuda.synchronize()
+    t_plain_graph = e0.elapsed_time(e1) / reps
+    cnt_h = cnts.cpu().tolist()
+    identical = all(torch.equal(batched[i], outs[i][: cnt_h[i]]) for i in range(len(specs)))
+    # oracle on a sample of tasks
+    rng = np.random.default_rng(0)
+    sample = sorted(rng.choice(len(specs), 6, replace=False).tolist())
+    ok = True
+    for i in sample:
+        s = specs[i]
+        yh = ys[i].cpu().numpy()
+        exp = getattr(oracle, s["algo"])(yh, s["n_out"])
+        ok &= bool(np.array_equal(batched[i].cpu().numpy(), exp))
+    b.close()
+    return {
+        "workload": "512 series, lengths log-uniform 1e4..2e7 (sum %d points, %.2f GB), dtypes f32/f16/i16/u8, "
+                    "MinMax / M4 alternating, n_out 500..4000" % (sum(s["n"] for s in specs), total_bytes / 1e9),
+        "batched_ms": round(t_batch, 4), "batched_GBps": round(total_bytes / t_batch / 1e6, 1),
+        "plain_eager_ms": round(t_plain_eager, 4), "plain_eager_wall_ms": round(wall_plain, 4),
+        "plain_graph_ms": round(t_plain_graph, 4),
+        "speedup_vs_plain_eager": round(t_plain_eager / t_batch, 2),
+        "speedup_vs_plain_graph": round(t_plain_graph / t_batch, 2),
+        "identical_to_plain": identical, "oracle_sample_bit_exact": ok,
+        "tuning": {"chunk_bytes": tune[0], "small_bin": tune[1], "grid_blocks": tune[2]},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -106,6 +189,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="m4x", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the batched and served comparisons")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain device copy of y (for counter calibration)")
     args = ap.parse_args()
@@ -196,6 +280,10 @@ def main():
         cb, ref = cpu_baseline(args.workload, x, y, w)
         res["cpu_baseline"] = cb
         res["parity_vs_oracle"] = "bit-exact" if np.array_equal(ref, got) else "MISMATCH"
+    if not args.no_extra:
+        del yd, xd, ws
+        torch.cuda.empty_cache()
+        res["batched"] = bench_batched()
     print(json.dumps(res), flush=True)
 
 

@@ -207,6 +207,67 @@ int ts_batch_autotune(ts_plan *plan, int64_t *out_idx, int64_t *counts, void *ws
 
 void ts_plan_free(ts_plan *plan);
 
+/* ---- Serving: zoom/pan requests over series resident in HBM ------------ */
+
+typedef struct {
+  int32_t n_streams;     /* concurrent batches in flight (1..16), one HIP stream each */
+  int32_t max_batch;     /* requests per batch (1..32) */
+  int64_t max_nout;      /* largest n_out a request may ask for */
+  int64_t minmax_ratio;  /* MinMaxLTTB preselection ratio (1..30) */
+  int32_t plain;         /* 1: no batching -- each request alone, in arrival order, with
+                            ts_window + ts_minmaxlttb on one stream (baseline) */
+  size_t arena_bytes;    /* device workspace per stream; raised to at least one worst-case request */
+} ts_server_config;
+
+/* One finished request.  Its indices (into the full series, strictly
+ * increasing) are idx[offset .. offset+count) of the poll buffer. */
+typedef struct {
+  int64_t id;
+  int32_t series;
+  int32_t status;       /* TS_OK or the error of the batch it ran in */
+  int64_t count;
+  int64_t offset;
+  int64_t i0, i1;       /* the request's window [i0, i1) */
+  double t_submit;      /* ts_server_now() at submission */
+  double t_done;        /* ts_server_now() when the indices were in host memory */
+  int64_t batch_size;   /* requests in the batch it ran in */
+} ts_result;
+
+typedef struct ts_server ts_server;
+
+/* Starts a server over n_series resident series (device x, int32/int64/
+ * uint32/uint64, and y of any dtype; they must stay valid until
+ * ts_server_free).  A request (series, xa, xb, n_out) is MinMaxLTTB with
+ * cfg->minmax_ratio on the points with xa <= x <= xb, indices into the full
+ * series (the zoom/pan use of Sec. 1).  One scheduler thread admits pending
+ * requests oldest-first into free streams -- at most max_batch per batch and
+ * only while their worst-case workspace fits the stream's arena -- resolves
+ * their windows on the device, runs them as one batch (ts_batch_run's
+ * kernels) and copies the results back; batches on different streams overlap
+ * on the GPU, and requests that arrive meanwhile join the next free stream.
+ * Every result equals ts_minmaxlttb on its window alone.  Allocates the
+ * arenas and pinned buffers here; ts_server_free releases them. */
+int ts_server_create(const ts_series *series, int32_t n_series, const ts_server_config *cfg, ts_server **server);
+
+/* Queues a request; *req_id receives its id.  Thread-safe. */
+int ts_server_submit(ts_server *server, int32_t series, int64_t xa, int64_t xb, int64_t n_out, int64_t *req_id);
+
+/* Moves up to max_results finished requests out of the server: metadata to
+ * res[], indices to the host buffer idx (capacity idx_cap); *n_results =
+ * how many.  Thread-safe. */
+int ts_server_poll(ts_server *server, ts_result *res, int32_t max_results, int64_t *idx, int64_t idx_cap,
+                   int32_t *n_results);
+
+/* Counters; returns the last batch error (TS_OK if none). */
+int ts_server_stats(ts_server *server, int64_t *batches, int64_t *max_batch, int64_t *requests_done,
+                    int64_t *pending);
+
+/* Seconds on the server's monotonic clock (the clock of t_submit/t_done). */
+double ts_server_now(void);
+
+/* Finishes every queued request, joins the scheduler, frees everything. */
+void ts_server_free(ts_server *server);
+
 /* Tuning knobs of the argmin/argmax pass, process-wide: chunk_bytes (a power
  * of two >= 4096; -1 = automatic) is the slice of y one wavefront reduces;
  * bin segments shorter than small_bin elements (-1 = default 128) are reduced

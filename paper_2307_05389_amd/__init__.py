@@ -16,6 +16,7 @@ from .api import (  # noqa: F401
 )
 from ._lib import TsArgError, TsError, lib  # noqa: F401
 from .batch import Batch  # noqa: F401
+from .serve import Server  # noqa: F401
 
 __all__ = ["minmax", "m4", "lttb", "minmaxlttb", "downsample_into", "workspace_bytes", "bin_edges",
-           "bin_argminmax", "lttb_centres", "window", "set_tuning", "Batch", "TsError", "TsArgError"]
+           "bin_argminmax", "lttb_centres", "window", "set_tuning", "Batch", "Server", "TsError", "TsArgError"]

@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "common.hpp"
+#include "batch_host.hpp"
 #include "internal.hpp"
 #include "tsds.h"
 
@@ -27,29 +28,6 @@ static size_t al256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 using namespace tsds;
 
-struct ts_plan {
-  std::vector<ts_task> in;
-  std::vector<BatchTask> tasks;
-  std::vector<int32_t> slot_task, lttb_tasks;
-  int64_t total_chunks = 0, total_slots = 0;
-  size_t ws_bytes = 0;      // for the largest chunk count in the tuning space
-  int64_t out_needed = 0;   // max(out_offset + n_out)
-  bool any_x = false;
-  int64_t max_m = 0;        // largest MinMaxLTTB candidate capacity
-  // tuning
-  int64_t chunk_bytes = 16384;
-  int32_t small = 128;
-  int64_t grid_blocks = 0;
-  // device table
-  void *d_table = nullptr;
-  size_t table_bytes = 0;
-  int device = 0;
-  // graph
-  hipStream_t cap_stream = nullptr;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-  const void *g_out = nullptr, *g_counts = nullptr, *g_ws = nullptr;
-};
 
 namespace {
 
@@ -57,8 +35,11 @@ const int64_t kMinChunk = 4096;
 
 size_t esize(int dt) { return elem_size(dt); }
 
-// Lay out every task for chunk size `chunk_bytes`; returns the workspace size.
-size_t layout(ts_plan *p, int64_t chunk_bytes) {
+}  // namespace
+
+namespace tsds {
+
+size_t batch_layout(ts_plan *p, int64_t chunk_bytes) {
   p->tasks.clear();
   p->slot_task.clear();
   p->lttb_tasks.clear();
@@ -66,6 +47,11 @@ size_t layout(ts_plan *p, int64_t chunk_bytes) {
   p->total_slots = 0;
   p->any_x = false;
   p->max_m = 0;
+  for (int g = 0; g < 11; g++) {
+    p->group_cb[g].clear();
+    p->group_tix[g].clear();
+    p->group_total[g] = 0;
+  }
   size_t o = 0;
   int64_t ti = 0;
   for (const ts_task &in : p->in) {
@@ -96,7 +82,7 @@ size_t layout(ts_plan *p, int64_t chunk_bytes) {
         t.n = s.n - 2;
       }
     }
-    t.chunk_begin = p->total_chunks;
+    t.chunk_begin = p->group_total[s.y_dtype];
     t.slot_begin = p->total_slots;
     if (t.mode == 0) {
       const int64_t es = (int64_t)esize(t.ydt);
@@ -121,6 +107,9 @@ size_t layout(ts_plan *p, int64_t chunk_bytes) {
       o = al256(o + 32 * (size_t)t.nb);
       t.o_cnt = (int64_t)o;
       o = al256(o + 8 * (size_t)t.nb);
+      p->group_cb[t.ydt].push_back(p->group_total[t.ydt]);
+      p->group_tix[t.ydt].push_back((int32_t)ti);
+      p->group_total[t.ydt] += t.nchunks;
       p->total_chunks += t.nchunks;
       p->total_slots += t.nb + 1;
       for (int64_t k = 0; k < t.nb + 1; k++) p->slot_task.push_back((int32_t)ti);
@@ -150,11 +139,38 @@ size_t layout(ts_plan *p, int64_t chunk_bytes) {
   return o;
 }
 
-int upload(ts_plan *p) {
+size_t batch_table_bytes(ts_plan *p) {
   const size_t a = al256(sizeof(BatchTask) * p->tasks.size());
   const size_t b = al256(sizeof(int32_t) * p->slot_task.size());
   const size_t c = al256(sizeof(int32_t) * p->lttb_tasks.size());
-  const size_t need = std::max<size_t>(a + b + c, 256);
+  size_t need = a + b + c;
+  for (int g = 0; g < 11; g++) {
+    p->group_off_cb[g] = need;
+    need += al256(sizeof(int64_t) * p->group_cb[g].size());
+    p->group_off_tix[g] = need;
+    need += al256(sizeof(int32_t) * p->group_tix[g].size());
+  }
+  return std::max<size_t>(need, 256);
+}
+
+void batch_pack_table(const ts_plan *p, char *h) {
+  const size_t a = al256(sizeof(BatchTask) * p->tasks.size());
+  const size_t b = al256(sizeof(int32_t) * p->slot_task.size());
+  memcpy(h, p->tasks.data(), sizeof(BatchTask) * p->tasks.size());
+  memcpy(h + a, p->slot_task.data(), sizeof(int32_t) * p->slot_task.size());
+  memcpy(h + a + b, p->lttb_tasks.data(), sizeof(int32_t) * p->lttb_tasks.size());
+  for (int g = 0; g < 11; g++) {
+    memcpy(h + p->group_off_cb[g], p->group_cb[g].data(), sizeof(int64_t) * p->group_cb[g].size());
+    memcpy(h + p->group_off_tix[g], p->group_tix[g].data(), sizeof(int32_t) * p->group_tix[g].size());
+  }
+}
+
+}  // namespace tsds
+
+namespace {
+
+int upload(ts_plan *p) {
+  const size_t need = batch_table_bytes(p);
   hipError_t e;
   if (need > p->table_bytes) {
     if (p->d_table) (void)hipFree(p->d_table);
@@ -163,21 +179,19 @@ int upload(ts_plan *p) {
     p->table_bytes = need;
   }
   std::vector<char> h(need, 0);
-  memcpy(h.data(), p->tasks.data(), sizeof(BatchTask) * p->tasks.size());
-  memcpy(h.data() + a, p->slot_task.data(), sizeof(int32_t) * p->slot_task.size());
-  memcpy(h.data() + a + b, p->lttb_tasks.data(), sizeof(int32_t) * p->lttb_tasks.size());
+  batch_pack_table(p, h.data());
   if ((e = hipMemcpy(p->d_table, h.data(), need, hipMemcpyHostToDevice)) != hipSuccess)
     return api_fail(TS_ERR_HIP, "plan table upload failed");
   return TS_OK;
 }
 
-BatchArgs args(const ts_plan *p, int64_t *out, int64_t *counts, void *ws) {
+BatchArgs args(const ts_plan *p, const void *d_table, int64_t *out, int64_t *counts, void *ws) {
   BatchArgs a;
   const size_t ta = al256(sizeof(BatchTask) * p->tasks.size());
   const size_t tb = al256(sizeof(int32_t) * p->slot_task.size());
-  a.tasks = (const BatchTask *)p->d_table;
-  a.slot_task = (const int32_t *)((const char *)p->d_table + ta);
-  a.lttb_tasks = (const int32_t *)((const char *)p->d_table + ta + tb);
+  a.tasks = (const BatchTask *)d_table;
+  a.slot_task = (const int32_t *)((const char *)d_table + ta);
+  a.lttb_tasks = (const int32_t *)((const char *)d_table + ta + tb);
   a.ntasks = (int64_t)p->tasks.size();
   a.total_chunks = p->total_chunks;
   a.total_slots = p->total_slots;
@@ -192,15 +206,34 @@ BatchArgs args(const ts_plan *p, int64_t *out, int64_t *counts, void *ws) {
   return a;
 }
 
-int enqueue(const ts_plan *p, int64_t *out, int64_t *counts, void *ws, hipStream_t st) {
-  const BatchArgs a = args(p, out, counts, ws);
+}  // namespace
+
+int tsds::batch_enqueue(const ts_plan *p, const void *d_table, int64_t *out, int64_t *counts, void *ws,
+                        hipStream_t st) {
+  const BatchArgs a = args(p, d_table, out, counts, ws);
   hipError_t e;
   if (p->any_x && (e = launch_batch_edges(a, st)) != hipSuccess) return api_fail(TS_ERR_HIP, "batch edges launch failed");
-  if ((e = launch_batch_scan(a, p->grid_blocks, st)) != hipSuccess) return api_fail(TS_ERR_HIP, "batch scan launch failed");
+  for (int g = 0; g < 11; g++) {
+    if (p->group_total[g] == 0) continue;
+    BatchGroup bg;
+    bg.cb = (const int64_t *)((const char *)d_table + p->group_off_cb[g]);
+    bg.tix = (const int32_t *)((const char *)d_table + p->group_off_tix[g]);
+    bg.ntasks = (int64_t)p->group_cb[g].size();
+    bg.total = p->group_total[g];
+    bg.ydt = g;
+    if ((e = launch_batch_scan(a, bg, p->grid_blocks, st)) != hipSuccess)
+      return api_fail(TS_ERR_HIP, "batch scan launch failed");
+  }
   if ((e = launch_batch_merge(a, st)) != hipSuccess) return api_fail(TS_ERR_HIP, "batch merge launch failed");
   if ((e = launch_batch_compact(a, st)) != hipSuccess) return api_fail(TS_ERR_HIP, "batch compact launch failed");
   if ((e = launch_batch_lttb(a, st)) != hipSuccess) return api_fail(TS_ERR_HIP, "batch lttb launch failed");
   return TS_OK;
+}
+
+namespace {
+
+int enqueue(const ts_plan *p, int64_t *out, int64_t *counts, void *ws, hipStream_t st) {
+  return batch_enqueue(p, p->d_table, out, counts, ws, st);
 }
 
 void drop_graph(ts_plan *p) {
@@ -244,6 +277,17 @@ std::string signature(const ts_plan *p) {
 
 }  // namespace
 
+int tsds::batch_check_task(const ts_task &t) {
+  int rc;
+  if (t.algo != TS_MINMAX && t.algo != TS_M4 && t.algo != TS_MINMAXLTTB)
+    return api_fail(TS_ERR_ARG, "batched tasks are MinMax, M4 or MinMaxLTTB");
+  if ((rc = api_check_series(&t.series)) || (rc = api_check_nout(t.algo, t.n_out, t.minmax_ratio))) return rc;
+  if (t.algo == TS_MINMAXLTTB && t.minmax_ratio > 30)
+    return api_fail(TS_ERR_ARG, "batched MinMaxLTTB needs minmax_ratio <= 30");
+  if (t.out_offset < 0) return api_fail(TS_ERR_ARG, "out_offset < 0");
+  return TS_OK;
+}
+
 extern "C" {
 
 int ts_batch_plan(const ts_task *tasks, int64_t n_tasks, ts_plan **out_plan) {
@@ -255,21 +299,9 @@ int ts_batch_plan(const ts_task *tasks, int64_t n_tasks, ts_plan **out_plan) {
   for (int64_t i = 0; i < n_tasks; i++) {
     const ts_task &t = tasks[i];
     int rc;
-    if (t.algo != TS_MINMAX && t.algo != TS_M4 && t.algo != TS_MINMAXLTTB) {
-      delete p;
-      return api_fail(TS_ERR_ARG, "batched tasks are MinMax, M4 or MinMaxLTTB");
-    }
-    if ((rc = api_check_series(&t.series)) || (rc = api_check_nout(t.algo, t.n_out, t.minmax_ratio))) {
+    if ((rc = batch_check_task(t))) {
       delete p;
       return rc;
-    }
-    if (t.algo == TS_MINMAXLTTB && t.minmax_ratio > 30) {
-      delete p;
-      return api_fail(TS_ERR_ARG, "batched MinMaxLTTB needs minmax_ratio <= 30");
-    }
-    if (t.out_offset < 0) {
-      delete p;
-      return api_fail(TS_ERR_ARG, "out_offset < 0");
     }
     p->out_needed = std::max(p->out_needed, t.out_offset + t.n_out);
     p->in.push_back(t);
@@ -281,8 +313,8 @@ int ts_batch_plan(const ts_task *tasks, int64_t n_tasks, ts_plan **out_plan) {
     return api_fail(TS_ERR_HIP, "no HIP device");
   }
   p->grid_blocks = (int64_t)cus * 6;
-  p->ws_bytes = layout(p, kMinChunk);        // largest chunk count of the tuning space
-  layout(p, p->chunk_bytes);
+  p->ws_bytes = batch_layout(p, kMinChunk);        // largest chunk count of the tuning space
+  batch_layout(p, p->chunk_bytes);
   int rc = upload(p);
   if (rc) {
     if (p->d_table) (void)hipFree(p->d_table);
@@ -306,7 +338,7 @@ int ts_batch_set_tuning(ts_plan *p, int64_t chunk_bytes, int32_t small_bin, int6
   p->chunk_bytes = chunk_bytes;
   p->small = small_bin;
   p->grid_blocks = grid_blocks;
-  layout(p, chunk_bytes);
+  batch_layout(p, chunk_bytes);
   drop_graph(p);
   return upload(p);
 }

@@ -2,13 +2,18 @@
 // of series of uneven length, dtype and n_out in one pass.
 //
 // The host plan (api_batch.cpp) lays every series out as a run of equal-byte
-// chunks in one global work list (per-task offset table `chunk_begin`) and
-// one global list of bin slots (`slot_begin`, nb + 1 slots per task).
+// chunks in the work list of its element type (per-task offset table
+// `chunk_begin`) and one global list of bin slots (`slot_begin`, nb + 1
+// slots per task).
 //   k_batch_edges   one wavefront per bin slot of every task with x.
-//   k_batch_scan    persistent: a fixed grid of wavefronts, each taking one
-//                   contiguous range of the global work list and walking the
-//                   task table as it crosses series boundaries; each item is
-//                   the same per-chunk reduction as the single-series scan.
+//   k_batch_scan<T> persistent, one launch per element type present: a
+//                   fixed grid of wavefronts, each taking one contiguous
+//                   range of that type's work list and walking the task list
+//                   as it crosses series boundaries; each item is the same
+//                   per-chunk reduction as the single-series scan.  One
+//                   launch per type keeps each kernel's registers to its own
+//                   type (a runtime type switch would size every wavefront
+//                   for the widest path).
 //   k_batch_merge   one wavefront per bin slot: merge + per-bin selection.
 //   k_batch_compact one workgroup per task: scan of the per-bin counts and
 //                   the compacted output (or MinMaxLTTB candidates).
@@ -32,6 +37,25 @@ __device__ inline ScanParams task_scan_params(const BatchArgs &a, const BatchTas
   sp.binres = (int64_t *)(a.ws + t.o_binres);
   sp.partL = (Partial *)(a.ws + t.o_partL);
   sp.partR = (Partial *)(a.ws + t.o_partR);
+  sp.small = small;
+  sp.variant = 3;
+  return sp;
+}
+
+// The same, with every field read from the task table made wave-uniform.
+__device__ inline ScanParams task_scan_params_uniform(char *ws, const BatchTask *__restrict__ t, int32_t small) {
+  ScanParams sp;
+  sp.y = uniform(t->y);
+  sp.n = uniform(t->n);
+  sp.shift = uniform(t->shift);
+  sp.chunk = uniform(t->chunk);
+  sp.nchunks = uniform(t->nchunks);
+  const void *x = uniform(t->x);
+  sp.edges = x ? (const int64_t *)(ws + uniform(t->o_edges)) : nullptr;
+  sp.nb = uniform(t->nb);
+  sp.binres = (int64_t *)(ws + uniform(t->o_binres));
+  sp.partL = (Partial *)(ws + uniform(t->o_partL));
+  sp.partR = (Partial *)(ws + uniform(t->o_partR));
   sp.small = small;
   sp.variant = 3;
   return sp;
@@ -67,57 +91,69 @@ hipError_t launch_batch_edges(const BatchArgs &a, hipStream_t st) {
   return hipGetLastError();
 }
 
-// Last task whose chunk_begin <= item (tasks without chunks share starts).
-__device__ int64_t task_of_item(const BatchArgs &a, int64_t item, int lane) {
-  int64_t lo = 0, hi = a.ntasks;  // tasks[lo].chunk_begin <= item < tasks[hi].chunk_begin
+// Position k in the group's task list of the last task whose first work item
+// is <= item (tasks without items share their successor's start).
+__device__ int64_t group_pos_of_item(const int64_t *__restrict__ cb, int64_t ntasks, int64_t item, int lane) {
+  int64_t lo = 0, hi = ntasks;  // cb[lo] <= item < cb[hi]
   while (hi - lo > 1) {
     const int64_t step = (hi - lo + 63) / 64;
     const int64_t q = lo + (int64_t)lane * step;
-    const bool le = q < hi && a.tasks[q].chunk_begin <= item;
+    const bool le = q < hi && cb[q] <= item;
     const int cnt = __builtin_popcountll(ballot(le));
     const int64_t nlo = lo + (int64_t)(cnt - 1) * step;
     const int64_t nhi = lo + (int64_t)cnt * step;
     lo = nlo;
     hi = nhi < hi ? nhi : hi;
   }
-  while (lo + 1 < a.ntasks && a.tasks[lo + 1].chunk_begin <= item) lo++;
+  while (lo + 1 < ntasks && uniform(cb[lo + 1]) <= item) lo++;
   return lo;
 }
 
-__global__ __launch_bounds__(256) void k_batch_scan(BatchArgs a) {
+// Persistent scan over one dtype group: a fixed grid of wavefronts, each
+// taking one contiguous range of the group's work list.  Every item looks its
+// task up again (two 64-wide probes of the L2-resident offset table) so that
+// only the item index lives across iterations: carrying the task's
+// parameters through the loop would push wave-uniform state out of scalar
+// registers and double the vector registers per wavefront.
+template <typename T>
+__global__ __launch_bounds__(256) void k_batch_scan(const BatchTask *__restrict__ tasks, const int64_t *__restrict__ cb,
+                                                    const int32_t *__restrict__ tix, int64_t ntasks, int64_t total,
+                                                    char *ws, int32_t small) {
   const int lane = lane_id();
   const int64_t W = (int64_t)gridDim.x * 4;
   const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int64_t i0 = a.total_chunks * w / W, i1 = a.total_chunks * (w + 1) / W;
-  if (i0 >= i1) return;
-  int64_t t = task_of_item(a, i0, lane);
+  const int64_t i0 = total * w / W, i1 = total * (w + 1) / W;
+#pragma nounroll
   for (int64_t item = i0; item < i1; item++) {
-    while (t + 1 < a.ntasks && a.tasks[t + 1].chunk_begin <= item) t++;
-    const BatchTask &tk = a.tasks[t];
-    const ScanParams sp = task_scan_params(a, tk, a.small);
-    const int64_t c = item - tk.chunk_begin;
-    switch (tk.ydt) {
-      case TS_I8: scan_chunk<int8_t, 2, 2>(sp, c, lane); break;
-      case TS_I16: scan_chunk<int16_t, 2, 2>(sp, c, lane); break;
-      case TS_I32: scan_chunk<int32_t, 2, 2>(sp, c, lane); break;
-      case TS_I64: scan_chunk<int64_t, 2, 2>(sp, c, lane); break;
-      case TS_U8: scan_chunk<uint8_t, 2, 2>(sp, c, lane); break;
-      case TS_U16: scan_chunk<uint16_t, 2, 2>(sp, c, lane); break;
-      case TS_U32: scan_chunk<uint32_t, 2, 2>(sp, c, lane); break;
-      case TS_U64: scan_chunk<uint64_t, 2, 2>(sp, c, lane); break;
-      case TS_F16: scan_chunk<half_t, 2, 2>(sp, c, lane); break;
-      case TS_F32: scan_chunk<float, 2, 2>(sp, c, lane); break;
-      case TS_F64: scan_chunk<double, 2, 2>(sp, c, lane); break;
-    }
+    const int64_t k = uniform(group_pos_of_item(cb, ntasks, item, lane));
+    const BatchTask *tk = tasks + uniform(tix[k]);
+    const ScanParams sp = task_scan_params_uniform(ws, tk, small);
+    scan_chunk<T, 2, 2>(sp, item - uniform(tk->chunk_begin), lane);
   }
 }
 
-hipError_t launch_batch_scan(const BatchArgs &a, int64_t grid_blocks, hipStream_t st) {
-  if (a.total_chunks == 0) return hipSuccess;
-  int64_t g = grid_blocks;
-  if (g > (a.total_chunks + 3) / 4) g = (a.total_chunks + 3) / 4;
-  if (g < 1) g = 1;
-  k_batch_scan<<<dim3((unsigned)g), dim3(256), 0, st>>>(a);
+hipError_t launch_batch_scan(const BatchArgs &a, const BatchGroup &g, int64_t grid_blocks, hipStream_t st) {
+  if (g.total == 0) return hipSuccess;
+  int64_t gb = grid_blocks;
+  if (gb > (g.total + 3) / 4) gb = (g.total + 3) / 4;
+  if (gb < 1) gb = 1;
+  dim3 grid((unsigned)gb), block(256);
+#define TSDS_BATCH_ARGS a.tasks, g.cb, g.tix, g.ntasks, g.total, a.ws, a.small
+  switch (g.ydt) {
+    case TS_I8: k_batch_scan<int8_t><<<grid, block, 0, st>>>(TSDS_BATCH_ARGS); break;
+    case TS_I16: k_batch_scan<int16_t><<<grid, block, 0, st>>>(TSDS_BATCH_ARGS); break;
+    case TS_I32: k_batch_scan<int32_t><<<grid, block, 0, st>>>(TSDS_BATCH_ARGS); break;
+    case TS_I64: k_batch_scan<int64_t><<<grid, block, 0, st>>>(TSDS_BATCH_ARGS); break;
+    case TS_U8: k_batch_scan<uint8_t><<<grid, block, 0, st>>>(TSDS_BATCH_ARGS); break;
+    case TS_U16: k_batch_scan<uint16_t><<<grid, block, 0, st>>>(TSDS_BATCH_ARGS); break;
+    case TS_U32: k_batch_scan<uint32_t><<<grid, block, 0, st>>>(TSDS_BATCH_ARGS); break;
+    case TS_U64: k_batch_scan<uint64_t><<<grid, block, 0, st>>>(TSDS_BATCH_ARGS); break;
+    case TS_F16: k_batch_scan<half_t><<<grid, block, 0, st>>>(TSDS_BATCH_ARGS); break;
+    case TS_F32: k_batch_scan<float><<<grid, block, 0, st>>>(TSDS_BATCH_ARGS); break;
+    case TS_F64: k_batch_scan<double><<<grid, block, 0, st>>>(TSDS_BATCH_ARGS); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef TSDS_BATCH_ARGS
   return hipGetLastError();
 }
 

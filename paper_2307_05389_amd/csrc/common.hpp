@@ -213,6 +213,20 @@ template <typename C> __device__ inline C wave_max(C x) {
 
 __device__ inline uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
+// Mark a value wave-uniform (it is kept in scalar registers from then on).
+template <typename V>
+__device__ inline V uniform(V v) {
+  static_assert(sizeof(V) == 4 || sizeof(V) == 8, "4 or 8 byte values");
+  if constexpr (sizeof(V) == 8) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((int)(uint32_t)u);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((int)(uint32_t)(u >> 32));
+    return __builtin_bit_cast(V, ((uint64_t)hi << 32) | lo);
+  } else {
+    return __builtin_bit_cast(V, (uint32_t)__builtin_amdgcn_readfirstlane((int)__builtin_bit_cast(uint32_t, v)));
+  }
+}
+
 template <typename C>
 __device__ inline C readlane(C v, int lane) {
   if constexpr (sizeof(C) == 8) {

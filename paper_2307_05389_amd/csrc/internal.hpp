@@ -105,7 +105,7 @@ struct BatchTask {
   int32_t algo;         // TS_MINMAX, TS_M4, TS_MINMAXLTTB
   int32_t mode;         // 0: scan; 1: n <= n_out (all indices); 2: MinMaxLTTB without preselection
   int64_t shift, chunk, nchunks, nb;
-  int64_t chunk_begin;  // first global work item (chunk) of this task
+  int64_t chunk_begin;  // first work item (chunk) of this task in its dtype group's list
   int64_t slot_begin;   // first global bin slot (nb + 1 slots per task)
   int64_t n_out, out_offset;
   int64_t o_edges, o_binres, o_partL, o_partR, o_sel, o_cnt;
@@ -130,9 +130,38 @@ struct BatchArgs {
 };
 
 hipError_t launch_batch_edges(const BatchArgs &a, hipStream_t st);
-hipError_t launch_batch_scan(const BatchArgs &a, int64_t grid_blocks, hipStream_t st);
+// Work list of one dtype group: the group's tasks in order (tix) and the
+// first work item of each (cb, non-decreasing), total items.
+struct BatchGroup {
+  const int64_t *cb;
+  const int32_t *tix;
+  int64_t ntasks;
+  int64_t total;
+  int32_t ydt;
+};
+
+hipError_t launch_batch_scan(const BatchArgs &a, const BatchGroup &g, int64_t grid_blocks, hipStream_t st);
 hipError_t launch_batch_merge(const BatchArgs &a, hipStream_t st);
 hipError_t launch_batch_compact(const BatchArgs &a, hipStream_t st);
 hipError_t launch_batch_lttb(const BatchArgs &a, hipStream_t st);
+
+}  // namespace tsds
+
+namespace tsds {
+
+// Zoom windows of up to kMaxWindows requests: ranges[2i], ranges[2i+1] =
+// [i0, i1) of the points of request i with xa <= x <= xb (integer x).
+constexpr int kMaxWindows = 32;
+struct WindowBatch {
+  const void *x[kMaxWindows];
+  int64_t n[kMaxWindows];
+  int64_t xa[kMaxWindows];
+  int64_t xb[kMaxWindows];
+  int32_t xdt[kMaxWindows];
+  int32_t count;
+  int64_t *ranges;
+};
+
+hipError_t launch_windows(const WindowBatch &wb, hipStream_t st);
 
 }  // namespace tsds

@@ -181,35 +181,55 @@ hipError_t launch_compact(const CompactParams &p, hipStream_t st) {
 
 // ------------------------------------------------------------------ window
 
+// First index i in [0, n) with x[i] >= xa (w = 0) or x[i] > xb (w = 1), by a
+// 64-ary wavefront search; values are compared in 64 bits (int64 or uint64).
 template <typename X>
-__global__ void k_window(const X *x, int64_t n, int64_t xa, int64_t xb, int64_t *range) {
+__device__ int64_t window_bound(const X *x, int64_t n, int64_t xa, int64_t xb, int w, int lane) {
   using K = typename XKey<X>::K;
-  const int lane = lane_id();
-  const int w = threadIdx.x >> 6;
-  // wave 0: first index with x >= xa; wave 1: first index with x > xb
-  // (= first index with x >= xb + 1 for integers; xb + 1 saturates).
-  K v;
   if (w == 0) {
-    v = (K)xa;
-    if (std::is_unsigned<K>::value && xa < 0) v = 0;
-  } else {
-    if (std::is_unsigned<K>::value && xb < 0) v = 0;
-    else v = (K)xb == (K)(std::numeric_limits<K>::max()) ? (K)xb : (K)((K)xb + 1);
+    if (std::is_unsigned<K>::value && xa < 0) return 0;
+    return wave_lower_bound<X, K>(x, 0, n, (K)xa, lane);
   }
-  int64_t r = wave_lower_bound<X, K>(x, 0, n, v, lane);
-  if (w == 1 && !(std::is_unsigned<K>::value && xb < 0) && (K)xb == std::numeric_limits<K>::max()) r = n;
+  if (std::is_unsigned<K>::value && xb < 0) return 0;
+  if ((K)xb == std::numeric_limits<K>::max()) return n;
+  return wave_lower_bound<X, K>(x, 0, n, (K)((K)xb + 1), lane);
+}
+
+__device__ int64_t window_bound_any(const void *x, int xdt, int64_t n, int64_t xa, int64_t xb, int w, int lane) {
+  switch (xdt) {
+    case TS_I32: return window_bound<int32_t>((const int32_t *)x, n, xa, xb, w, lane);
+    case TS_I64: return window_bound<int64_t>((const int64_t *)x, n, xa, xb, w, lane);
+    case TS_U32: return window_bound<uint32_t>((const uint32_t *)x, n, xa, xb, w, lane);
+    case TS_U64: return window_bound<uint64_t>((const uint64_t *)x, n, xa, xb, w, lane);
+  }
+  return 0;
+}
+
+__global__ void k_window(const void *x, int xdt, int64_t n, int64_t xa, int64_t xb, int64_t *range) {
+  const int lane = lane_id(), w = threadIdx.x >> 6;
+  const int64_t r = window_bound_any(x, xdt, n, xa, xb, w, lane);
   if (lane == 0) range[w] = r;
 }
 
 hipError_t launch_window(const void *x, int xdt, int64_t n, int64_t xa, int64_t xb, int64_t *range,
                          hipStream_t st) {
-  switch (xdt) {
-    case TS_I32: k_window<int32_t><<<1, 128, 0, st>>>((const int32_t *)x, n, xa, xb, range); break;
-    case TS_I64: k_window<int64_t><<<1, 128, 0, st>>>((const int64_t *)x, n, xa, xb, range); break;
-    case TS_U32: k_window<uint32_t><<<1, 128, 0, st>>>((const uint32_t *)x, n, xa, xb, range); break;
-    case TS_U64: k_window<uint64_t><<<1, 128, 0, st>>>((const uint64_t *)x, n, xa, xb, range); break;
-    default: return hipErrorInvalidValue;
-  }
+  if (xdt != TS_I32 && xdt != TS_I64 && xdt != TS_U32 && xdt != TS_U64) return hipErrorInvalidValue;
+  k_window<<<1, 128, 0, st>>>(x, xdt, n, xa, xb, range);
+  return hipGetLastError();
+}
+
+// One workgroup of two wavefronts per request.
+__global__ void k_windows(WindowBatch wb) {
+  const int i = blockIdx.x;
+  if (i >= wb.count) return;
+  const int lane = lane_id(), w = threadIdx.x >> 6;
+  const int64_t r = window_bound_any(wb.x[i], wb.xdt[i], wb.n[i], wb.xa[i], wb.xb[i], w, lane);
+  if (lane == 0) wb.ranges[2 * i + w] = r;
+}
+
+hipError_t launch_windows(const WindowBatch &wb, hipStream_t st) {
+  if (wb.count <= 0) return hipSuccess;
+  k_windows<<<dim3((unsigned)wb.count), dim3(128), 0, st>>>(wb);
   return hipGetLastError();
 }
 

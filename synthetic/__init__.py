@@ -189,3 +189,21 @@ def device_timestamps(n, seed, gap_max=100, device="cuda", chunk=1 << 26):
         out[s:e] = c
         del c
     return out
+
+
+def device_walk_cast(n, dtype, seed, device="cuda"):
+    """Random walk generated on the GPU in float64 (torch Philox), then cast
+    like cast_walk: floats round to nearest, integers are rounded and clipped
+    (unsigned shifted to mid-range).  `dtype` is a numpy dtype."""
+    import torch
+    dtype = np.dtype(dtype)
+    tdt = {np.dtype(np.float16): torch.float16, np.dtype(np.float32): torch.float32,
+           np.dtype(np.float64): torch.float64, np.dtype(np.int8): torch.int8, np.dtype(np.int16): torch.int16,
+           np.dtype(np.int32): torch.int32, np.dtype(np.int64): torch.int64, np.dtype(np.uint8): torch.uint8}[dtype]
+    w = device_walk(n, seed, device, dtype=torch.float64)
+    if dtype.kind == "f":
+        return w.to(tdt)
+    lo, hi = _INT_RANGES[dtype]
+    if dtype.kind == "u":
+        w += (hi + 1) / 2
+    return torch.clamp(torch.round(w), lo, hi).to(tdt)
