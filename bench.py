@@ -182,6 +182,104 @@ def bench_batched(seed=3, n_series=512, reps=10):
     }
 
 
+def bench_served(full=False, n_series=64, n_points=200_000_000):
+    """Serving: 64 resident series of 2e8 float32 points with int64 timestamps
+    (gaps 1..100); Poisson arrivals of zoom/pan requests (window width
+    log-uniform 0.1%..100% of the range, n_out 800..4000, MinMaxLTTB ratio 4);
+    latency from the scheduled arrival to the indices in host memory."""
+    import torch
+    import paper_2307_05389_amd as tsds
+    import synthetic as S
+    log(f"[bench] served: generating {n_series} x {n_points:,} points on the GPU")
+    series = []
+    for s in range(n_series):
+        x = S.device_timestamps(n_points, 10_000 + s, gap_max=100)
+        y = S.device_walk(n_points, 20_000 + s)
+        series.append((x, y))
+    torch.cuda.synchronize()
+    x_first = [int(x[0].item()) for x, _ in series]
+    x_last = [int(x[-1].item()) for x, _ in series]
+    resident_gb = sum(x.numel() * 8 + y.numel() * 4 for x, y in series) / 1e9
+    qps_list = [100.0, 1000.0, 5000.0, 20000.0] if full else [1000.0, 5000.0, 20000.0]
+    n_req = 10000 if full else 2000
+    n_warm = 500 if full else 200
+
+    def run(srv, qps, seed):
+        reqs = S.zoom_requests(n_req + n_warm, n_series, x_first, x_last, seed=seed, qps=qps)
+        t0 = srv.now() + 0.05
+        sched = {}
+        done = {}
+        k = 0
+        while len(done) < len(reqs):
+            now = srv.now()
+            while k < len(reqs) and now >= t0 + reqs[k]["t"]:
+                q = reqs[k]
+                rid = srv.submit(q["series"], q["xa"], q["xb"], q["n_out"])
+                sched[rid] = (t0 + q["t"], k)
+                k += 1
+                now = srv.now()
+            for r in srv.poll():
+                done[r["id"]] = r
+            if k < len(reqs):
+                wait = t0 + reqs[k]["t"] - srv.now()
+                if wait > 2e-4:
+                    time.sleep(min(wait - 1e-4, 1e-3))
+            elif len(done) < len(reqs):
+                time.sleep(2e-4)
+        lat, pts, bs = [], 0, []
+        first, last = None, 0.0
+        by_k = {}
+        for rid, r in done.items():
+            ta, kk = sched[rid]
+            by_k[kk] = r
+            if kk < n_warm:
+                continue
+            lat.append(r["t_done"] - ta)
+            pts += r["i1"] - r["i0"]
+            bs.append(r["batch_size"])
+            first = ta if first is None else min(first, ta)
+            last = max(last, r["t_done"])
+        lat = np.array(lat) * 1e3
+        return {"qps": qps, "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                "points_per_s": round(pts / (last - first), 1),
+                "mean_batch": round(float(np.mean(bs)), 2)}, by_k, reqs
+
+    out = {"workload": f"{n_series} resident series x {n_points:,} float32 points + int64 timestamps "
+                       f"({resident_gb:.1f} GB), MinMaxLTTB ratio 4, n_out 800..4000, {n_req} requests "
+                       f"(+{n_warm} warm-up) per rate", "served": [], "plain": []}
+    srv = tsds.Server(series, n_streams=4, max_batch=32, max_nout=4000, minmax_ratio=4)
+    served_first = None
+    for i, qps in enumerate(qps_list):
+        log(f"[bench] served at {qps} QPS")
+        stats, by_k, reqs = run(srv, qps, seed=4 + i)
+        out["served"].append(stats)
+        if i == 0:
+            served_first = (by_k, reqs)
+    srv.close()
+    plain = tsds.Server(series, plain=True, max_nout=4000, minmax_ratio=4)
+    log(f"[bench] plain FIFO at {qps_list[0]} QPS")
+    stats, pk, _ = run(plain, qps_list[0], seed=4)
+    out["plain"].append(stats)
+    plain.close()
+    by_k, reqs = served_first
+    out["identical_served_vs_plain"] = all(np.array_equal(by_k[k]["indices"], pk[k]["indices"]) for k in by_k)
+    # oracle on a few requests (window copied to the host)
+    import oracle
+    ok = True
+    for k in (n_warm, n_warm + 1, n_warm + 2):
+        r, q = by_k[k], reqs[k]
+        x, y = series[q["series"]]
+        xh = x[r["i0"]: r["i1"]].cpu().numpy()
+        yh = y[r["i0"]: r["i1"]].cpu().numpy()
+        exp = r["i0"] + oracle.minmaxlttb(yh, q["n_out"], 4, x=xh)
+        ok &= bool(np.array_equal(exp, r["indices"]))
+    out["oracle_sample_bit_exact"] = ok
+    del series
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -190,6 +288,7 @@ def main():
     ap.add_argument("--workload", default="m4x", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the batched and served comparisons")
+    ap.add_argument("--serve-full", action="store_true", help="served sweep at 100..20000 QPS, 10000 requests each")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain device copy of y (for counter calibration)")
     args = ap.parse_args()
@@ -284,6 +383,8 @@ def main():
         del yd, xd, ws
         torch.cuda.empty_cache()
         res["batched"] = bench_batched()
+        torch.cuda.empty_cache()
+        res["served"] = bench_served(full=args.serve_full)
     print(json.dumps(res), flush=True)
 
 

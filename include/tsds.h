@@ -216,7 +216,8 @@ typedef struct {
   int64_t minmax_ratio;  /* MinMaxLTTB preselection ratio (1..30) */
   int32_t plain;         /* 1: no batching -- each request alone, in arrival order, with
                             ts_window + ts_minmaxlttb on one stream (baseline) */
-  size_t arena_bytes;    /* device workspace per stream; raised to at least one worst-case request */
+  size_t arena_bytes;    /* device workspace per stream (0: max_batch worst-case requests);
+                            raised to at least one worst-case request */
 } ts_server_config;
 
 /* One finished request.  Its indices (into the full series, strictly
@@ -273,10 +274,13 @@ void ts_server_free(ts_server *server);
  * bin segments shorter than small_bin elements (-1 = default 128) are reduced
  * one bin per lane instead of one bin per wavefront; scan_variant (-1 =
  * default, 0..3) picks the tile shape (16-byte vectors per lane per tile and
- * tiles in flight: 0 = 4x2, 1 = 4x1, 2 = 8x1, 3 = 2x2).  Results never depend
- * on them; workspace sizes do, so query ts_workspace_bytes after a change.
- * Not thread-safe with concurrent compute calls. */
-int ts_set_tuning(int64_t chunk_bytes, int32_t small_bin, int32_t scan_variant);
+ * tiles in flight: 0 = 4x2, 1 = 4x1, 2 = 8x1, 3 = 2x2); stage (-1 = automatic:
+ * on when bins average < 4096 elements, 0 = off, 1 = on) copies each chunk to
+ * LDS first and reduces its bins from there (chunk_bytes <= 32768 when on).
+ * Results never depend on them; workspace sizes do, so query
+ * ts_workspace_bytes after a change.  Not thread-safe with concurrent
+ * compute calls. */
+int ts_set_tuning(int64_t chunk_bytes, int32_t small_bin, int32_t scan_variant, int32_t stage);
 
 /* Host-side query: the tile variant and chunk size (bytes) the scan uses for
  * n elements of y_dtype under the current tuning. */

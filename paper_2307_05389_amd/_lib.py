@@ -69,7 +69,7 @@ def lib():
         L.ts_lttb_centres.restype = ctypes.c_int
         L.ts_window.argtypes = [SP, i64, i64, vp, vp]
         L.ts_window.restype = ctypes.c_int
-        L.ts_set_tuning.argtypes = [i64, i32, i32]
+        L.ts_set_tuning.argtypes = [i64, i32, i32, i32]
         L.ts_set_tuning.restype = ctypes.c_int
         L.ts_scan_config.argtypes = [ctypes.c_int, i64, ctypes.POINTER(ctypes.c_int32),
                                      ctypes.POINTER(ctypes.c_int64)]

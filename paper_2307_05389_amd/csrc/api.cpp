@@ -62,35 +62,47 @@ static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 struct ScanShape {
   int32_t variant;
   int64_t chunk_bytes;
+  int32_t stage;
 };
 
 static ScanShape default_shape(int ydt) {
   switch (ydt) {
-    case TS_U8: return {3, 16384};
-    case TS_I8: return {0, 65536};
-    case TS_I16: case TS_U16: case TS_F16: return {0, 16384};
-    case TS_I32: case TS_U32: case TS_F32: return {2, 16384};
-    default: return {2, 32768};
+    case TS_U8: return {3, 16384, 0};
+    case TS_I8: return {0, 65536, 0};
+    case TS_I16: case TS_U16: case TS_F16: return {0, 16384, 0};
+    case TS_I32: case TS_U32: case TS_F32: return {2, 16384, 0};
+    default: return {2, 32768, 0};
   }
 }
 
 static int64_t g_chunk_bytes_override = -1;
 static int32_t g_small_override = -1;
 static int32_t g_variant_override = -1;
+static int32_t g_stage_override = -1;
 
-static ScanShape scan_shape(int ydt, int64_t n) {
+// Bins averaging fewer than kStageBin elements go through LDS-staged chunks
+// of kStageChunk bytes (one HBM round trip per chunk instead of one per bin).
+static const int64_t kStageBin = 4096, kStageChunk = 8192;
+
+static ScanShape scan_shape(int ydt, int64_t n, int64_t nb) {
   ScanShape sh = default_shape(ydt);
   if (g_variant_override >= 0) sh.variant = g_variant_override;
+  sh.stage = g_stage_override >= 0 ? g_stage_override : (nb > 0 && n / nb < kStageBin ? 1 : 0);
   if (g_chunk_bytes_override > 0) {
     sh.chunk_bytes = g_chunk_bytes_override;
+  } else if (sh.stage) {
+    sh.chunk_bytes = kStageChunk;
   } else {
     const int64_t total = n * (int64_t)elem_size(ydt);
     while (sh.chunk_bytes > 4096 && total / sh.chunk_bytes < 4096) sh.chunk_bytes /= 2;
   }
+  if (sh.stage && sh.chunk_bytes > 32768) sh.chunk_bytes = 32768;  // LDS per workgroup
   return sh;
 }
 
-static int64_t chunk_elems(int ydt, int64_t n) { return scan_shape(ydt, n).chunk_bytes / (int64_t)elem_size(ydt); }
+static int64_t chunk_elems(int ydt, int64_t n, int64_t nb) {
+  return scan_shape(ydt, n, nb).chunk_bytes / (int64_t)elem_size(ydt);
+}
 
 static hipEvent_t g_ev_start = nullptr, g_ev_stop = nullptr;
 
@@ -109,7 +121,7 @@ struct ScanPlan {
 static ScanPlan scan_plan(int ydt, int64_t n, int64_t nb, bool need_edges, size_t base) {
   ScanPlan p;
   p.nb = nb;
-  p.chunk = chunk_elems(ydt, n);
+  p.chunk = chunk_elems(ydt, n, nb);
   p.nchunks = (n + vec_width(ydt) - 1 + p.chunk - 1) / p.chunk;
   if (p.nchunks < 1) p.nchunks = 1;
   size_t o = base;
@@ -244,7 +256,8 @@ static int run_scan(const ts_series &s, int64_t nb, int m4, const ScanPlan &pl, 
   sp.partL = (Partial *)wsp(ws, pl.off_partL);
   sp.partR = (Partial *)wsp(ws, pl.off_partR);
   sp.small = small_threshold();
-  sp.variant = scan_shape(s.y_dtype, s.n).variant;
+  sp.variant = scan_shape(s.y_dtype, s.n, nb).variant;
+  sp.stage = scan_shape(s.y_dtype, s.n, nb).stage;
   if (g_ev_start && (e = hipEventRecord(g_ev_start, st)) != hipSuccess) return hip_fail(e, "event");
   if ((e = launch_scan(s.y_dtype, sp, st)) != hipSuccess) return hip_fail(e, "scan");
   if (g_ev_stop && (e = hipEventRecord(g_ev_stop, st)) != hipSuccess) return hip_fail(e, "event");
@@ -484,7 +497,8 @@ int ts_bin_argminmax(const ts_series *s, const int64_t *edges, int64_t nb, int64
   sp.partL = (Partial *)wsp(ws, pl.off_partL);
   sp.partR = (Partial *)wsp(ws, pl.off_partR);
   sp.small = small_threshold();
-  sp.variant = scan_shape(s->y_dtype, s->n).variant;
+  sp.variant = scan_shape(s->y_dtype, s->n, nb).variant;
+  sp.stage = scan_shape(s->y_dtype, s->n, nb).stage;
   hipError_t e;
   if ((e = launch_scan(s->y_dtype, sp, st)) != hipSuccess) return hip_fail(e, "scan");
   MergeParams mp{};
@@ -535,20 +549,22 @@ int ts_window(const ts_series *s, int64_t xa, int64_t xb, int64_t *range, void *
 }
 
 // Tuning knobs (tests use them to show that results do not depend on them).
-int ts_set_tuning(int64_t chunk_bytes, int32_t small_bin, int32_t scan_variant) {
+int ts_set_tuning(int64_t chunk_bytes, int32_t small_bin, int32_t scan_variant, int32_t stage) {
   if (chunk_bytes > 0 && (chunk_bytes < 4096 || (chunk_bytes & (chunk_bytes - 1))))
     return fail(TS_ERR_ARG, "chunk_bytes must be a power of two >= 4096");
   if (scan_variant > 3) return fail(TS_ERR_ARG, "scan_variant must be -1..3");
+  if (stage > 1) return fail(TS_ERR_ARG, "stage must be -1, 0 or 1");
   g_chunk_bytes_override = chunk_bytes;
   g_small_override = small_bin;
   g_variant_override = scan_variant;
+  g_stage_override = stage;
   return TS_OK;
 }
 
 int ts_scan_config(int y_dtype, int64_t n, int32_t *variant, int64_t *chunk_bytes) {
   if (elem_size(y_dtype) == 0) return fail(TS_ERR_DTYPE, "y dtype %d is not a ts dtype", y_dtype);
   if (!variant || !chunk_bytes) return fail(TS_ERR_NULL, "variant / chunk_bytes is NULL");
-  const ScanShape sh = scan_shape(y_dtype, n);
+  const ScanShape sh = scan_shape(y_dtype, n, 1);
   *variant = sh.variant;
   *chunk_bytes = sh.chunk_bytes;
   return TS_OK;

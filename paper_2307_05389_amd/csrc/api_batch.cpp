@@ -32,6 +32,7 @@ using namespace tsds;
 namespace {
 
 const int64_t kMinChunk = 4096;
+const int64_t kStageBin = 4096, kStageChunk = 8192;
 
 size_t esize(int dt) { return elem_size(dt); }
 
@@ -47,7 +48,7 @@ size_t batch_layout(ts_plan *p, int64_t chunk_bytes) {
   p->total_slots = 0;
   p->any_x = false;
   p->max_m = 0;
-  for (int g = 0; g < 11; g++) {
+  for (int g = 0; g < 22; g++) {
     p->group_cb[g].clear();
     p->group_tix[g].clear();
     p->group_total[g] = 0;
@@ -82,12 +83,16 @@ size_t batch_layout(ts_plan *p, int64_t chunk_bytes) {
         t.n = s.n - 2;
       }
     }
-    t.chunk_begin = p->group_total[s.y_dtype];
     t.slot_begin = p->total_slots;
+    int grp = 0;
     if (t.mode == 0) {
       const int64_t es = (int64_t)esize(t.ydt);
       t.nb = in.algo == TS_MINMAX ? in.n_out / 2 : in.algo == TS_M4 ? in.n_out / 4 : in.n_out * in.minmax_ratio / 2;
-      t.chunk = chunk_bytes / es;
+      // bins averaging fewer than kStageBin elements: LDS-staged chunks
+      t.stage = t.n / t.nb < kStageBin ? 1 : 0;
+      t.chunk = (t.stage ? kStageChunk : chunk_bytes) / es;
+      grp = t.ydt + 11 * t.stage;
+      t.chunk_begin = p->group_total[grp];
       t.shift = (int64_t)(((uintptr_t)t.y & 15) / (uintptr_t)es);
       t.nchunks = (t.n + t.shift + t.chunk - 1) / t.chunk;
       // workspace regions (sized for the smallest chunk of the tuning space)
@@ -107,9 +112,9 @@ size_t batch_layout(ts_plan *p, int64_t chunk_bytes) {
       o = al256(o + 32 * (size_t)t.nb);
       t.o_cnt = (int64_t)o;
       o = al256(o + 8 * (size_t)t.nb);
-      p->group_cb[t.ydt].push_back(p->group_total[t.ydt]);
-      p->group_tix[t.ydt].push_back((int32_t)ti);
-      p->group_total[t.ydt] += t.nchunks;
+      p->group_cb[grp].push_back(p->group_total[grp]);
+      p->group_tix[grp].push_back((int32_t)ti);
+      p->group_total[grp] += t.nchunks;
       p->total_chunks += t.nchunks;
       p->total_slots += t.nb + 1;
       for (int64_t k = 0; k < t.nb + 1; k++) p->slot_task.push_back((int32_t)ti);
@@ -144,7 +149,7 @@ size_t batch_table_bytes(ts_plan *p) {
   const size_t b = al256(sizeof(int32_t) * p->slot_task.size());
   const size_t c = al256(sizeof(int32_t) * p->lttb_tasks.size());
   size_t need = a + b + c;
-  for (int g = 0; g < 11; g++) {
+  for (int g = 0; g < 22; g++) {
     p->group_off_cb[g] = need;
     need += al256(sizeof(int64_t) * p->group_cb[g].size());
     p->group_off_tix[g] = need;
@@ -159,7 +164,7 @@ void batch_pack_table(const ts_plan *p, char *h) {
   memcpy(h, p->tasks.data(), sizeof(BatchTask) * p->tasks.size());
   memcpy(h + a, p->slot_task.data(), sizeof(int32_t) * p->slot_task.size());
   memcpy(h + a + b, p->lttb_tasks.data(), sizeof(int32_t) * p->lttb_tasks.size());
-  for (int g = 0; g < 11; g++) {
+  for (int g = 0; g < 22; g++) {
     memcpy(h + p->group_off_cb[g], p->group_cb[g].data(), sizeof(int64_t) * p->group_cb[g].size());
     memcpy(h + p->group_off_tix[g], p->group_tix[g].data(), sizeof(int32_t) * p->group_tix[g].size());
   }
@@ -213,14 +218,15 @@ int tsds::batch_enqueue(const ts_plan *p, const void *d_table, int64_t *out, int
   const BatchArgs a = args(p, d_table, out, counts, ws);
   hipError_t e;
   if (p->any_x && (e = launch_batch_edges(a, st)) != hipSuccess) return api_fail(TS_ERR_HIP, "batch edges launch failed");
-  for (int g = 0; g < 11; g++) {
+  for (int g = 0; g < 22; g++) {
     if (p->group_total[g] == 0) continue;
     BatchGroup bg;
     bg.cb = (const int64_t *)((const char *)d_table + p->group_off_cb[g]);
     bg.tix = (const int32_t *)((const char *)d_table + p->group_off_tix[g]);
     bg.ntasks = (int64_t)p->group_cb[g].size();
     bg.total = p->group_total[g];
-    bg.ydt = g;
+    bg.ydt = g % 11;
+    bg.stage = g / 11;
     if ((e = launch_batch_scan(a, bg, p->grid_blocks, st)) != hipSuccess)
       return api_fail(TS_ERR_HIP, "batch scan launch failed");
   }

@@ -39,6 +39,7 @@ __device__ inline ScanParams task_scan_params(const BatchArgs &a, const BatchTas
   sp.partR = (Partial *)(a.ws + t.o_partR);
   sp.small = small;
   sp.variant = 3;
+  sp.stage = t.stage;
   return sp;
 }
 
@@ -58,6 +59,7 @@ __device__ inline ScanParams task_scan_params_uniform(char *ws, const BatchTask 
   sp.partR = (Partial *)(ws + uniform(t->o_partR));
   sp.small = small;
   sp.variant = 3;
+  sp.stage = uniform(t->stage);
   return sp;
 }
 
@@ -132,12 +134,55 @@ __global__ __launch_bounds__(256) void k_batch_scan(const BatchTask *__restrict_
   }
 }
 
+// The same over a group of staged tasks (chunks copied to LDS first).
+template <typename T>
+__global__ __launch_bounds__(256) void k_batch_scan_staged(const BatchTask *__restrict__ tasks,
+                                                           const int64_t *__restrict__ cb,
+                                                           const int32_t *__restrict__ tix, int64_t ntasks,
+                                                           int64_t total, char *ws, int32_t small, int64_t lds_per) {
+  extern __shared__ u32x4 stage_lds[];
+  const int lane = lane_id();
+  const int64_t W = (int64_t)gridDim.x * 4;
+  const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t i0 = total * w / W, i1 = total * (w + 1) / W;
+  u32x4 *lds = stage_lds + (threadIdx.x >> 6) * lds_per;
+#pragma nounroll
+  for (int64_t item = i0; item < i1; item++) {
+    const int64_t k = uniform(group_pos_of_item(cb, ntasks, item, lane));
+    const BatchTask *tk = tasks + uniform(tix[k]);
+    const ScanParams sp = task_scan_params_uniform(ws, tk, small);
+    scan_chunk_staged<T>(sp, item - uniform(tk->chunk_begin), lane, lds);
+  }
+}
+
 hipError_t launch_batch_scan(const BatchArgs &a, const BatchGroup &g, int64_t grid_blocks, hipStream_t st) {
   if (g.total == 0) return hipSuccess;
   int64_t gb = grid_blocks;
   if (gb > (g.total + 3) / 4) gb = (g.total + 3) / 4;
   if (gb < 1) gb = 1;
   dim3 grid((unsigned)gb), block(256);
+  if (g.stage) {
+    // staged chunks are 8 KiB: 8192 / sizeof(T) elements, 513 vectors per wavefront
+    const int64_t per = 8192 / 16 + 1;
+    const size_t lds = 4 * sizeof(u32x4) * (size_t)per;
+#define TSDS_STAGED(T) k_batch_scan_staged<T><<<grid, block, lds, st>>>(a.tasks, g.cb, g.tix, g.ntasks, g.total, a.ws, a.small, per)
+    switch (g.ydt) {
+      case TS_I8: TSDS_STAGED(int8_t); break;
+      case TS_I16: TSDS_STAGED(int16_t); break;
+      case TS_I32: TSDS_STAGED(int32_t); break;
+      case TS_I64: TSDS_STAGED(int64_t); break;
+      case TS_U8: TSDS_STAGED(uint8_t); break;
+      case TS_U16: TSDS_STAGED(uint16_t); break;
+      case TS_U32: TSDS_STAGED(uint32_t); break;
+      case TS_U64: TSDS_STAGED(uint64_t); break;
+      case TS_F16: TSDS_STAGED(half_t); break;
+      case TS_F32: TSDS_STAGED(float); break;
+      case TS_F64: TSDS_STAGED(double); break;
+      default: return hipErrorInvalidValue;
+    }
+#undef TSDS_STAGED
+    return hipGetLastError();
+  }
 #define TSDS_BATCH_ARGS a.tasks, g.cb, g.tix, g.ntasks, g.total, a.ws, a.small
   switch (g.ydt) {
     case TS_I8: k_batch_scan<int8_t><<<grid, block, 0, st>>>(TSDS_BATCH_ARGS); break;

@@ -15,11 +15,12 @@ struct ts_plan {
   std::vector<tsds::BatchTask> tasks;
   std::vector<int32_t> slot_task, lttb_tasks;
   int64_t total_chunks = 0, total_slots = 0;
-  // per element type: task list and first work items
-  std::vector<int64_t> group_cb[11];
-  std::vector<int32_t> group_tix[11];
-  int64_t group_total[11] = {0};
-  size_t group_off_cb[11] = {0}, group_off_tix[11] = {0};
+  // per (element type, staged): task list and first work items; group
+  // g = dtype + 11 * staged
+  std::vector<int64_t> group_cb[22];
+  std::vector<int32_t> group_tix[22];
+  int64_t group_total[22] = {0};
+  size_t group_off_cb[22] = {0}, group_off_tix[22] = {0};
   size_t ws_bytes = 0;      // for the largest chunk count in the tuning space
   int64_t out_needed = 0;   // max(out_offset + n_out)
   bool any_x = false;

@@ -27,6 +27,7 @@ struct ScanParams {
   Partial *partR;         // [nchunks] bin that continues after the chunk
   int32_t small;          // segments shorter than this: one lane per bin
   int32_t variant;        // tile shape (see launch_scan)
+  int32_t stage;          // 1: chunks go through LDS (many small bins per chunk)
 };
 
 struct MergeParams {
@@ -104,6 +105,8 @@ struct BatchTask {
   int32_t ydt, xdt;
   int32_t algo;         // TS_MINMAX, TS_M4, TS_MINMAXLTTB
   int32_t mode;         // 0: scan; 1: n <= n_out (all indices); 2: MinMaxLTTB without preselection
+  int32_t stage;        // 1: staged chunks (many small bins)
+  int32_t pad_;
   int64_t shift, chunk, nchunks, nb;
   int64_t chunk_begin;  // first work item (chunk) of this task in its dtype group's list
   int64_t slot_begin;   // first global bin slot (nb + 1 slots per task)
@@ -138,6 +141,7 @@ struct BatchGroup {
   int64_t ntasks;
   int64_t total;
   int32_t ydt;
+  int32_t stage;
 };
 
 hipError_t launch_batch_scan(const BatchArgs &a, const BatchGroup &g, int64_t grid_blocks, hipStream_t st);

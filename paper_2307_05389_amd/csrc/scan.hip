@@ -72,6 +72,11 @@ hipError_t launch_edges_x(const void *x, int xdt, int64_t n, int64_t nb, int64_t
 template <typename T>
 static hipError_t scan_t(const ScanParams &p, hipStream_t st) {
   dim3 grid((unsigned)((p.nchunks + 3) / 4)), block(256);
+  if (p.stage) {
+    const size_t lds = 4 * sizeof(u32x4) * (size_t)staged_lds_vectors(p.chunk, 16 / (int)sizeof(T));
+    k_scan_staged<T><<<grid, block, lds, st>>>(p);
+    return hipGetLastError();
+  }
   switch (p.variant) {
     case 0: k_scan<T, 4, 2><<<grid, block, 0, st>>>(p); break;
     case 1: k_scan<T, 4, 1><<<grid, block, 0, st>>>(p); break;

@@ -504,6 +504,118 @@ __device__ void scan_chunk(const ScanParams &p, int64_t c, int lane) {
   }
 }
 
+// ---- staged chunks (many small bins) ---------------------------------------
+//
+// The whole chunk is first copied into the wavefront's LDS slice with
+// coalesced 16-byte loads (all issued together), then every bin segment of
+// the chunk is reduced from LDS: one lane per segment for segments shorter
+// than kStageLane elements (64 segments per wavefront at a time), the whole
+// wavefront for longer ones.  A chunk holding hundreds of bins thus costs one
+// HBM round trip instead of one per bin.  `lds` holds chunk/VEC + 1 vectors.
+
+constexpr int64_t kStageLane = 512;
+
+template <typename T>
+__device__ void scan_chunk_staged(const ScanParams &p, int64_t c, int lane, u32x4 *lds) {
+  using E = Elem<T>;
+  using C = typename E::C;
+  constexpr int VEC = 16 / (int)sizeof(T);
+  const T *__restrict__ y = (const T *)p.y;
+  const u32x4 *__restrict__ base = (const u32x4 *)(y - p.shift);
+  int64_t c0 = c * p.chunk - p.shift;
+  if (c0 < 0) c0 = 0;
+  int64_t c1 = (c + 1) * p.chunk - p.shift;
+  if (c1 > p.n) c1 = p.n;
+  if (p.edges) {
+    const int64_t e0 = p.edges[0], en = p.edges[p.nb];
+    if (c0 < e0) c0 = e0;
+    if (c1 > en) c1 = en;
+  }
+  if (c0 >= c1) return;
+  const int64_t vc0 = (c0 + p.shift) / VEC, vc1 = (c1 + p.shift + VEC - 1) / VEC;
+  const int64_t nv = vc1 - vc0;
+  for (int64_t k0 = 0; k0 < nv; k0 += (int64_t)kWave * 8) {
+    u32x4 d[8];
+#pragma unroll
+    for (int u = 0; u < 8; u++) {
+      const int64_t v = k0 + u * kWave + lane;
+      d[u] = v < nv ? __builtin_nontemporal_load(base + vc0 + v) : u32x4{0u, 0u, 0u, 0u};
+    }
+#pragma unroll
+    for (int u = 0; u < 8; u++) {
+      const int64_t v = k0 + u * kWave + lane;
+      if (v < nv) lds[v] = d[u];
+    }
+  }
+  // The wavefront's own LDS writes complete in order before its later LDS
+  // reads; the fences keep the compiler from moving the reads above them.
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  const T *lt = (const T *)lds;
+  const int64_t g_base = vc0 * VEC - p.shift;  // global index of lt[0]
+
+  int64_t b = first_bin(p.edges, p.n, p.nb, c0, lane);
+  for (;;) {
+    const int64_t bb = b + lane;
+    const bool inb = bb < p.nb;
+    const int64_t s = edge_at(p.edges, p.n, p.nb, bb);
+    const int64_t e = edge_at(p.edges, p.n, p.nb, bb + 1);
+    const int64_t lo = s > c0 ? s : c0;
+    const int64_t hi = e < c1 ? e : c1;
+    const bool valid = inb && lo < hi;
+    const bool before = s < c0, after = e > c1;
+    const bool small = valid && (hi - lo) < kStageLane;
+    if (small) {
+      const T *q = lt + (lo - g_base);
+      const int32_t len = (int32_t)(hi - lo);
+      C vmn = E::load(q), vmx = vmn;
+      int32_t jmn = 0, jmx = 0;
+      for (int32_t j = 1; j < len; j++) {
+        const C v = E::load(q + j);
+        if (v < vmn) { vmn = v; jmn = j; }
+        if (vmx < v) { vmx = v; jmx = j; }
+      }
+      write_result<T>(p, c, bb, before, after, vmn, lo + jmn, vmx, lo + jmx);
+    }
+    uint64_t big = ballot(valid && !small);
+    while (big) {
+      const int k = __builtin_ctzll(big);
+      big &= big - 1;
+      const int64_t slo = readlane(lo, k), shi = readlane(hi, k);
+      // per lane: elements slo + lane + 64 i in index order, strict compares
+      C vmn = E::highest(), vmx = E::lowest();
+      int64_t imn = INT64_MAX, imx = INT64_MAX;
+      for (int64_t i = slo + lane; i < shi; i += kWave) {
+        const C v = E::load(lt + (i - g_base));
+        if (imn == INT64_MAX || v < vmn) { vmn = v; imn = i; }
+        if (imx == INT64_MAX || vmx < v) { vmx = v; imx = i; }
+      }
+      const C wmn = wave_min(vmn), wmx = wave_max(vmx);
+      const int64_t rmn = wave_min(imn != INT64_MAX && vmn == wmn ? imn : INT64_MAX);
+      const int64_t rmx = wave_min(imx != INT64_MAX && vmx == wmx ? imx : INT64_MAX);
+      const bool sb = readlane(s, k) < c0, sa = readlane(e, k) > c1;
+      if (lane == 0) write_result<T>(p, c, b + k, sb, sa, wmn, rmn, wmx, rmx);
+    }
+    const int64_t e63 = readlane(e, 63);
+    if (e63 >= c1 || b + kWave >= p.nb) break;
+    b += kWave;
+  }
+}
+
+// LDS vectors one wavefront needs for a staged chunk of `chunk` elements.
+__host__ __device__ inline int64_t staged_lds_vectors(int64_t chunk_elems, int vec) { return chunk_elems / vec + 1; }
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_scan_staged(ScanParams p) {
+  extern __shared__ u32x4 stage_lds[];
+  const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (c >= p.nchunks) return;
+  constexpr int VEC = 16 / (int)sizeof(T);
+  const int64_t per = staged_lds_vectors(p.chunk, VEC);
+  scan_chunk_staged<T>(p, c, lane_id(), stage_lds + (threadIdx.x >> 6) * per);
+}
+
 template <typename T, int U, int NB>
 __global__ __launch_bounds__(256) void k_scan(ScanParams p) {
   const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);

@@ -368,7 +368,8 @@ int ts_server_create(const ts_series *series, int32_t n_series, const ts_server_
     sv->ws_series.push_back(w);
     sv->ws_per_request_max = std::max(sv->ws_per_request_max, w);
   }
-  // the arena must hold at least one worst-case request
+  // default arena: max_batch worst-case requests; never below one
+  if (sv->cfg.arena_bytes == 0) sv->cfg.arena_bytes = sv->ws_per_request_max * (size_t)sv->cfg.max_batch;
   if (sv->cfg.arena_bytes < sv->ws_per_request_max) sv->cfg.arena_bytes = sv->ws_per_request_max;
   int cus = 256;
   if (hipGetDevice(&sv->device) != hipSuccess ||

@@ -114,18 +114,21 @@ def test_ties_signed_zero_and_extremes(ts, oracle_mod):
                 assert np.array_equal(gpu(ts, algo, y, n_out), orc(oracle_mod, algo, y, n_out)), (name, algo, n_out)
 
 
-@pytest.mark.parametrize("chunk,small", [(4096, -1), (4096, 1), (65536, 100000), (8192, 7), (-1, 1 << 20)])
-def test_tuning_does_not_change_results(ts, oracle_mod, chunk, small):
-    """Chunk size and the one-lane-per-bin threshold only change the work
-    split (bins split over many chunks, many bins per wavefront)."""
-    ts.set_tuning(chunk, small)
+@pytest.mark.parametrize("chunk,small,stage", [(4096, -1, 0), (4096, 1, 0), (65536, 100000, 0), (8192, 7, 0),
+                                               (-1, 1 << 20, 0), (8192, -1, 1), (4096, -1, 1), (32768, -1, 1),
+                                               (-1, -1, -1)])
+def test_tuning_does_not_change_results(ts, oracle_mod, chunk, small, stage):
+    """Chunk size, the one-lane-per-bin threshold and LDS staging only change
+    the work split (bins split over many chunks, many bins per wavefront,
+    bins reduced from LDS)."""
+    ts.set_tuning(chunk, small, -1, stage)
     try:
         for dtype in (np.float32, np.uint8, np.float64, np.int16):
             y = S.walk(250007, dtype, seed=5)
             x = S.timestamps(250007, 50, seed=6)
             for algo, n_out in (("minmax", 2), ("minmax", 600), ("m4", 40000), ("m4", 8)):
                 for xx in (None, x):
-                    say(f"[tuning] chunk={chunk} small={small} {np.dtype(dtype).name} {algo} {n_out}")
+                    say(f"[tuning] chunk={chunk} small={small} stage={stage} {np.dtype(dtype).name} {algo} {n_out}")
                     assert np.array_equal(gpu(ts, algo, y, n_out, xx), orc(oracle_mod, algo, y, n_out, xx))
     finally:
         ts.set_tuning()
