@@ -58,7 +58,7 @@ def make_inputs(name):
 
 def scan_source_hash():
     h = hashlib.sha256()
-    for f in ("scan.hip", "common.hpp"):
+    for f in ("scan.hip", "scan_core.hpp", "common.hpp"):
         with open(os.path.join(ROOT, "paper_2307_05389_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -350,7 +350,9 @@ def main():
     got = out[: int(cnt.item())].cpu().numpy()
     log(f"[bench] {ms_step:.4f} ms/step, scan kernel {scan_ms:.4f} ms ({achieved:.0f} GB/s)")
 
-    variant, chunk_bytes, kernel = L.scan_config(yd.dtype, w["n"] if w["algo"] != "minmaxlttb" else w["n"] - 2)
+    nb = {"m4": w["n_out"] // 4, "minmax": w["n_out"] // 2, "minmaxlttb": w["n_out"] * 4 // 2}[w["algo"]]
+    variant, chunk_bytes, kernel = L.scan_config(yd.dtype, w["n"] if w["algo"] != "minmaxlttb" else w["n"] - 2,
+                                                 nb, None if xd is None else xd.dtype)
     traffic = load_traffic(kernel, args.workload)
     res = {
         "metric": "MinMax/M4 input GB/s vs HBM peak",

@@ -276,15 +276,22 @@ void ts_server_free(ts_server *server);
  * default, 0..3) picks the tile shape (16-byte vectors per lane per tile and
  * tiles in flight: 0 = 4x2, 1 = 4x1, 2 = 8x1, 3 = 2x2); stage (-1 = automatic:
  * on when bins average < 4096 elements, 0 = off, 1 = on) copies each chunk to
- * LDS first and reduces its bins from there (chunk_bytes <= 32768 when on).
+ * LDS first and reduces its bins from there (chunk_bytes <= 32768 when on);
+ * xclass (-1 = automatic: on for int64 x when bins average at least two
+ * chunks, 0 = off, 1 = on; int64 x and unstaged scans only) lets each chunk
+ * find its bins from x directly, so that the edge array is written by the scan
+ * instead of a separate edge search.
  * Results never depend on them; workspace sizes do, so query
  * ts_workspace_bytes after a change.  Not thread-safe with concurrent
  * compute calls. */
-int ts_set_tuning(int64_t chunk_bytes, int32_t small_bin, int32_t scan_variant, int32_t stage);
+int ts_set_tuning(int64_t chunk_bytes, int32_t small_bin, int32_t scan_variant, int32_t stage, int32_t xclass);
 
-/* Host-side query: the tile variant and chunk size (bytes) the scan uses for
- * n elements of y_dtype under the current tuning. */
-int ts_scan_config(int y_dtype, int64_t n, int32_t *variant, int64_t *chunk_bytes);
+/* Host-side query: the scan's tile variant, chunk size (bytes) and kind
+ * (0 = chunks with an edge array or closed-form bins, 1 = LDS-staged,
+ * 2 = classified from int64 x) for n elements of y_dtype in nb bins, x of
+ * x_dtype (TS_NONE: no x), under the current tuning. */
+int ts_scan_config(int y_dtype, int x_dtype, int64_t n, int64_t nb, int32_t *variant, int64_t *chunk_bytes,
+                   int32_t *kind);
 
 /* Timing hook: when both are non-NULL, the next compute calls record the
  * hipEvent_t `start` on their stream just before the argmin/argmax scan

@@ -69,10 +69,10 @@ def lib():
         L.ts_lttb_centres.restype = ctypes.c_int
         L.ts_window.argtypes = [SP, i64, i64, vp, vp]
         L.ts_window.restype = ctypes.c_int
-        L.ts_set_tuning.argtypes = [i64, i32, i32, i32]
+        L.ts_set_tuning.argtypes = [i64, i32, i32, i32, i32]
         L.ts_set_tuning.restype = ctypes.c_int
-        L.ts_scan_config.argtypes = [ctypes.c_int, i64, ctypes.POINTER(ctypes.c_int32),
-                                     ctypes.POINTER(ctypes.c_int64)]
+        L.ts_scan_config.argtypes = [ctypes.c_int, ctypes.c_int, i64, i64, ctypes.POINTER(ctypes.c_int32),
+                                     ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)]
         L.ts_scan_config.restype = ctypes.c_int
         L.ts_profile_scan_events.argtypes = [vp, vp]
         L.ts_profile_scan_events.restype = ctypes.c_int
@@ -85,12 +85,21 @@ CTYPE_NAME = {0: "signed char", 1: "short", 2: "int", 3: "long", 4: "unsigned ch
               6: "unsigned int", 7: "unsigned long", 8: "tsds::half_t", 9: "float", 10: "double"}
 
 
-def scan_config(dtype, n):
-    """(variant, chunk_bytes, kernel name) the scan uses for n elements."""
-    v, c = ctypes.c_int32(), ctypes.c_int64()
-    check(lib().ts_scan_config(DTYPE_CODES[dtype], int(n), ctypes.byref(v), ctypes.byref(c)))
-    u, nb = VARIANT_SHAPE[v.value]
-    return v.value, c.value, f"tsds::k_scan<{CTYPE_NAME[DTYPE_CODES[dtype]]}, {u}, {nb}>"
+SCAN_KINDS = {0: "k_scan", 1: "k_scan_staged", 2: "k_scan_xc"}
+
+
+def scan_config(dtype, n, nb=1, x_dtype=None):
+    """(variant, chunk_bytes, kernel name) the scan uses for n elements of
+    dtype in nb bins with x of x_dtype (None: no x)."""
+    v, c, k = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int32()
+    xd = TS_NONE if x_dtype is None else DTYPE_CODES[x_dtype]
+    check(lib().ts_scan_config(DTYPE_CODES[dtype], xd, int(n), int(nb), ctypes.byref(v), ctypes.byref(c),
+                               ctypes.byref(k)))
+    ct = CTYPE_NAME[DTYPE_CODES[dtype]]
+    if k.value == 1:
+        return v.value, c.value, f"tsds::k_scan_staged<{ct}>"
+    u, nbuf = VARIANT_SHAPE[v.value]
+    return v.value, c.value, f"tsds::{SCAN_KINDS[k.value]}<{ct}, {u}, {nbuf}>"
 
 
 def check(rc):

@@ -63,15 +63,16 @@ struct ScanShape {
   int32_t variant;
   int64_t chunk_bytes;
   int32_t stage;
+  int32_t xclass;  // chunks classified from int64 x, no separate edge search
 };
 
 static ScanShape default_shape(int ydt) {
   switch (ydt) {
-    case TS_U8: return {3, 16384, 0};
-    case TS_I8: return {0, 65536, 0};
-    case TS_I16: case TS_U16: case TS_F16: return {0, 16384, 0};
-    case TS_I32: case TS_U32: case TS_F32: return {2, 16384, 0};
-    default: return {2, 32768, 0};
+    case TS_U8: return {3, 16384, 0, 0};
+    case TS_I8: return {0, 65536, 0, 0};
+    case TS_I16: case TS_U16: case TS_F16: return {0, 16384, 0, 0};
+    case TS_I32: case TS_U32: case TS_F32: return {2, 16384, 0, 0};
+    default: return {2, 32768, 0, 0};
   }
 }
 
@@ -79,12 +80,17 @@ static int64_t g_chunk_bytes_override = -1;
 static int32_t g_small_override = -1;
 static int32_t g_variant_override = -1;
 static int32_t g_stage_override = -1;
+static int32_t g_xclass_override = -1;
 
 // Bins averaging fewer than kStageBin elements go through LDS-staged chunks
 // of kStageChunk bytes (one HBM round trip per chunk instead of one per bin).
 static const int64_t kStageBin = 4096, kStageChunk = 8192;
 
-static ScanShape scan_shape(int ydt, int64_t n, int64_t nb) {
+// Bins averaging at least kXclassChunks chunks are classified from int64 x
+// by the scan itself (the edge search would otherwise be a separate pass).
+static const int64_t kXclassChunks = 2;
+
+static ScanShape scan_shape(int ydt, int xdt, int64_t n, int64_t nb) {
   ScanShape sh = default_shape(ydt);
   if (g_variant_override >= 0) sh.variant = g_variant_override;
   sh.stage = g_stage_override >= 0 ? g_stage_override : (nb > 0 && n / nb < kStageBin ? 1 : 0);
@@ -97,11 +103,12 @@ static ScanShape scan_shape(int ydt, int64_t n, int64_t nb) {
     while (sh.chunk_bytes > 4096 && total / sh.chunk_bytes < 4096) sh.chunk_bytes /= 2;
   }
   if (sh.stage && sh.chunk_bytes > 32768) sh.chunk_bytes = 32768;  // LDS per workgroup
+  sh.xclass = 0;
+  if (xdt == TS_I64 && !sh.stage) {
+    const int64_t ce = sh.chunk_bytes / (int64_t)elem_size(ydt);
+    sh.xclass = g_xclass_override >= 0 ? g_xclass_override : (nb > 0 && n / nb >= kXclassChunks * ce ? 1 : 0);
+  }
   return sh;
-}
-
-static int64_t chunk_elems(int ydt, int64_t n, int64_t nb) {
-  return scan_shape(ydt, n, nb).chunk_bytes / (int64_t)elem_size(ydt);
 }
 
 static hipEvent_t g_ev_start = nullptr, g_ev_stop = nullptr;
@@ -112,16 +119,23 @@ static int32_t small_threshold() { return g_small_override > 0 ? g_small_overrid
 
 struct ScanPlan {
   int64_t nb = 0, chunk = 0, nchunks = 0;
-  size_t off_edges = 0, off_binres = 0, off_partL = 0, off_partR = 0, off_sel = 0, off_cnt = 0, bytes = 0;
+  int32_t variant = 0, stage = 0, xclass = 0;
+  size_t off_edges = 0, off_binres = 0, off_partL = 0, off_partR = 0, off_sel = 0, off_cnt = 0,
+         bytes = 0;
 };
 
 // Workspace of one argmin/argmax pass over n elements in nb bins.  The chunk
 // count allows for the largest possible misalignment of y, so the size does
 // not depend on the pointer.
-static ScanPlan scan_plan(int ydt, int64_t n, int64_t nb, bool need_edges, size_t base) {
+static ScanPlan scan_plan(int ydt, int xdt, int64_t n, int64_t nb, size_t base) {
   ScanPlan p;
+  const bool need_edges = xdt != TS_NONE;
+  const ScanShape sh = scan_shape(ydt, xdt, n, nb);
   p.nb = nb;
-  p.chunk = chunk_elems(ydt, n, nb);
+  p.chunk = sh.chunk_bytes / (int64_t)elem_size(ydt);
+  p.variant = sh.variant;
+  p.stage = sh.stage;
+  p.xclass = sh.xclass;
   p.nchunks = (n + vec_width(ydt) - 1 + p.chunk - 1) / p.chunk;
   if (p.nchunks < 1) p.nchunks = 1;
   size_t o = base;
@@ -238,10 +252,12 @@ static int64_t y_shift(const ts_series &s) {
 static int run_scan(const ts_series &s, int64_t nb, int m4, const ScanPlan &pl, void *ws, int64_t *out,
                     int64_t *out_count, int64_t index_offset, int64_t endpoints_n, hipStream_t st) {
   const int64_t *edges = nullptr;
+  int64_t *ed = nullptr;
   hipError_t e;
   if (s.x) {
-    int64_t *ed = (int64_t *)wsp(ws, pl.off_edges);
-    if ((e = launch_edges_x(s.x, s.x_dtype, s.n, nb, ed, st)) != hipSuccess) return hip_fail(e, "edges");
+    ed = (int64_t *)wsp(ws, pl.off_edges);
+    if (!pl.xclass && (e = launch_edges_x(s.x, s.x_dtype, s.n, nb, ed, st)) != hipSuccess)
+      return hip_fail(e, "edges");
     edges = ed;
   }
   ScanParams sp;
@@ -256,8 +272,12 @@ static int run_scan(const ts_series &s, int64_t nb, int m4, const ScanPlan &pl, 
   sp.partL = (Partial *)wsp(ws, pl.off_partL);
   sp.partR = (Partial *)wsp(ws, pl.off_partR);
   sp.small = small_threshold();
-  sp.variant = scan_shape(s.y_dtype, s.n, nb).variant;
-  sp.stage = scan_shape(s.y_dtype, s.n, nb).stage;
+  sp.variant = pl.variant;
+  sp.stage = pl.stage;
+  sp.xclass = pl.xclass;
+  sp.x = pl.xclass ? s.x : nullptr;
+  sp.xedges = pl.xclass ? ed : nullptr;
+  if (pl.xclass) sp.edges = nullptr;
   if (g_ev_start && (e = hipEventRecord(g_ev_start, st)) != hipSuccess) return hip_fail(e, "event");
   if ((e = launch_scan(s.y_dtype, sp, st)) != hipSuccess) return hip_fail(e, "scan");
   if (g_ev_stop && (e = hipEventRecord(g_ev_stop, st)) != hipSuccess) return hip_fail(e, "event");
@@ -273,7 +293,6 @@ static int run_scan(const ts_series &s, int64_t nb, int m4, const ScanPlan &pl, 
   mp.m4 = m4;
   mp.sel = (int64_t *)wsp(ws, pl.off_sel);
   mp.cnt = (int64_t *)wsp(ws, pl.off_cnt);
-  if ((e = launch_merge(mp, st)) != hipSuccess) return hip_fail(e, "merge");
   CompactParams cp;
   cp.nb = nb;
   cp.sel = mp.sel;
@@ -283,6 +302,7 @@ static int run_scan(const ts_series &s, int64_t nb, int m4, const ScanPlan &pl, 
   cp.index_offset = index_offset;
   cp.endpoints_n = endpoints_n;
   cp.all_n = -1;
+  if ((e = launch_merge(mp, st)) != hipSuccess) return hip_fail(e, "merge");
   if ((e = launch_compact(cp, st)) != hipSuccess) return hip_fail(e, "compact");
   return TS_OK;
 }
@@ -313,7 +333,7 @@ static MmlPlan mml_plan(const ts_series &s, int64_t n_out, int64_t ratio) {
   p.presel_all = ni <= npre;
   size_t o = 0;
   if (!p.presel_all) {
-    p.scan = scan_plan(s.y_dtype, ni, npre / 2, s.x != nullptr, 0);
+    p.scan = scan_plan(s.y_dtype, s.x_dtype, ni, npre / 2, 0);
     o = p.scan.bytes;
     p.off_cand = o;
     o = align256(o + sizeof(int64_t) * (size_t)(npre + 2));
@@ -382,8 +402,8 @@ size_t ts_workspace_bytes(int algo, const ts_series *s, int64_t n_out, int64_t m
   if (check_series(s) || check_nout(algo, n_out, minmax_ratio)) return 0;
   if (s->n <= n_out) return 0;
   switch (algo) {
-    case TS_MINMAX: return scan_plan(s->y_dtype, s->n, n_out / 2, s->x != nullptr, 0).bytes;
-    case TS_M4: return scan_plan(s->y_dtype, s->n, n_out / 4, s->x != nullptr, 0).bytes;
+    case TS_MINMAX: return scan_plan(s->y_dtype, s->x_dtype, s->n, n_out / 2, 0).bytes;
+    case TS_M4: return scan_plan(s->y_dtype, s->x_dtype, s->n, n_out / 4, 0).bytes;
     case TS_LTTB: return lttb_plan(s->n, n_out, 0).bytes;
     case TS_MINMAXLTTB: return mml_plan(*s, n_out, minmax_ratio).bytes;
   }
@@ -399,7 +419,7 @@ static int minmax_m4(int algo, const ts_series *s, int64_t n_out, int64_t *out_i
   if (s->n <= n_out) return write_all(s->n, out_idx, out_count, st);
   const int64_t nb = algo == TS_MINMAX ? n_out / 2 : n_out / 4;
   if ((rc = check_bins(s->n, nb))) return rc;
-  const ScanPlan pl = scan_plan(s->y_dtype, s->n, nb, s->x != nullptr, 0);
+  const ScanPlan pl = scan_plan(s->y_dtype, s->x_dtype, s->n, nb, 0);
   if ((rc = check_ws(ws, ws_bytes, pl.bytes))) return rc;
   return run_scan(*s, nb, algo == TS_M4, pl, ws, out_idx, out_count, 0, 0, st);
 }
@@ -473,7 +493,7 @@ int ts_bin_edges(const ts_series *s, int64_t nb, int64_t *edges, void *stream) {
 
 size_t ts_argminmax_workspace_bytes(const ts_series *s, int64_t nb) {
   if (check_series(s) || nb < 1) return 0;
-  return scan_plan(s->y_dtype, s->n, nb, false, 0).bytes;
+  return scan_plan(s->y_dtype, TS_NONE, s->n, nb, 0).bytes;
 }
 
 int ts_bin_argminmax(const ts_series *s, const int64_t *edges, int64_t nb, int64_t *imin, int64_t *imax, void *ws,
@@ -482,7 +502,7 @@ int ts_bin_argminmax(const ts_series *s, const int64_t *edges, int64_t nb, int64
   if ((rc = check_series(s)) || (rc = check_bins(s->n, nb))) return rc;
   if (!edges || !imin || !imax) return fail(TS_ERR_NULL, "edges / imin / imax is NULL");
   if (s->n == 0) return fail(TS_ERR_ARG, "empty series");
-  const ScanPlan pl = scan_plan(s->y_dtype, s->n, nb, false, 0);
+  const ScanPlan pl = scan_plan(s->y_dtype, TS_NONE, s->n, nb, 0);
   if ((rc = check_ws(ws, ws_bytes, pl.bytes))) return rc;
   hipStream_t st = (hipStream_t)stream;
   ScanParams sp;
@@ -497,8 +517,11 @@ int ts_bin_argminmax(const ts_series *s, const int64_t *edges, int64_t nb, int64
   sp.partL = (Partial *)wsp(ws, pl.off_partL);
   sp.partR = (Partial *)wsp(ws, pl.off_partR);
   sp.small = small_threshold();
-  sp.variant = scan_shape(s->y_dtype, s->n, nb).variant;
-  sp.stage = scan_shape(s->y_dtype, s->n, nb).stage;
+  sp.variant = pl.variant;
+  sp.stage = pl.stage;
+  sp.x = nullptr;
+  sp.xedges = nullptr;
+  sp.xclass = 0;
   hipError_t e;
   if ((e = launch_scan(s->y_dtype, sp, st)) != hipSuccess) return hip_fail(e, "scan");
   MergeParams mp{};
@@ -549,24 +572,30 @@ int ts_window(const ts_series *s, int64_t xa, int64_t xb, int64_t *range, void *
 }
 
 // Tuning knobs (tests use them to show that results do not depend on them).
-int ts_set_tuning(int64_t chunk_bytes, int32_t small_bin, int32_t scan_variant, int32_t stage) {
+int ts_set_tuning(int64_t chunk_bytes, int32_t small_bin, int32_t scan_variant, int32_t stage, int32_t xclass) {
   if (chunk_bytes > 0 && (chunk_bytes < 4096 || (chunk_bytes & (chunk_bytes - 1))))
     return fail(TS_ERR_ARG, "chunk_bytes must be a power of two >= 4096");
   if (scan_variant > 3) return fail(TS_ERR_ARG, "scan_variant must be -1..3");
   if (stage > 1) return fail(TS_ERR_ARG, "stage must be -1, 0 or 1");
+  if (xclass > 1) return fail(TS_ERR_ARG, "xclass must be -1, 0 or 1");
   g_chunk_bytes_override = chunk_bytes;
   g_small_override = small_bin;
   g_variant_override = scan_variant;
   g_stage_override = stage;
+  g_xclass_override = xclass;
   return TS_OK;
 }
 
-int ts_scan_config(int y_dtype, int64_t n, int32_t *variant, int64_t *chunk_bytes) {
+int ts_scan_config(int y_dtype, int x_dtype, int64_t n, int64_t nb, int32_t *variant, int64_t *chunk_bytes,
+                   int32_t *kind) {
   if (elem_size(y_dtype) == 0) return fail(TS_ERR_DTYPE, "y dtype %d is not a ts dtype", y_dtype);
-  if (!variant || !chunk_bytes) return fail(TS_ERR_NULL, "variant / chunk_bytes is NULL");
-  const ScanShape sh = scan_shape(y_dtype, n, 1);
+  if (x_dtype != TS_NONE && elem_size(x_dtype) == 0) return fail(TS_ERR_DTYPE, "x dtype %d is not a ts dtype", x_dtype);
+  if (!variant || !chunk_bytes || !kind) return fail(TS_ERR_NULL, "variant / chunk_bytes / kind is NULL");
+  if (nb < 1) return fail(TS_ERR_ARG, "need at least one bin");
+  const ScanShape sh = scan_shape(y_dtype, x_dtype, n, nb);
   *variant = sh.variant;
   *chunk_bytes = sh.chunk_bytes;
+  *kind = sh.stage ? 1 : sh.xclass ? 2 : 0;
   return TS_OK;
 }
 

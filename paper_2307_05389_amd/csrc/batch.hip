@@ -40,6 +40,9 @@ __device__ inline ScanParams task_scan_params(const BatchArgs &a, const BatchTas
   sp.small = small;
   sp.variant = 3;
   sp.stage = t.stage;
+  sp.x = nullptr;
+  sp.xedges = nullptr;
+  sp.xclass = 0;
   return sp;
 }
 
@@ -60,6 +63,9 @@ __device__ inline ScanParams task_scan_params_uniform(char *ws, const BatchTask 
   sp.small = small;
   sp.variant = 3;
   sp.stage = uniform(t->stage);
+  sp.x = nullptr;
+  sp.xedges = nullptr;
+  sp.xclass = 0;
   return sp;
 }
 

@@ -28,6 +28,9 @@ struct ScanParams {
   int32_t small;          // segments shorter than this: one lane per bin
   int32_t variant;        // tile shape (see launch_scan)
   int32_t stage;          // 1: chunks go through LDS (many small bins per chunk)
+  const void *x;          // int64 x when the chunks are classified from x (xclass), else NULL
+  int64_t *xedges;        // edge array the x-classified scan writes (nb + 1 entries)
+  int32_t xclass;
 };
 
 struct MergeParams {

@@ -77,6 +77,15 @@ static hipError_t scan_t(const ScanParams &p, hipStream_t st) {
     k_scan_staged<T><<<grid, block, lds, st>>>(p);
     return hipGetLastError();
   }
+  if (p.xclass) {
+    switch (p.variant) {
+      case 0: k_scan_xc<T, 4, 2><<<grid, block, 0, st>>>(p); break;
+      case 1: k_scan_xc<T, 4, 1><<<grid, block, 0, st>>>(p); break;
+      case 2: k_scan_xc<T, 8, 1><<<grid, block, 0, st>>>(p); break;
+      default: k_scan_xc<T, 2, 2><<<grid, block, 0, st>>>(p); break;
+    }
+    return hipGetLastError();
+  }
   switch (p.variant) {
     case 0: k_scan<T, 4, 2><<<grid, block, 0, st>>>(p); break;
     case 1: k_scan<T, 4, 1><<<grid, block, 0, st>>>(p); break;
@@ -105,10 +114,8 @@ hipError_t launch_scan(int ydt, const ScanParams &p, hipStream_t st) {
 
 // ------------------------------------------------------------------ merge
 
-__global__ __launch_bounds__(256) void k_merge(MergeParams p) {
-  const int lane = lane_id();
-  const int64_t bin = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (bin >= p.nb) return;
+// Merge + selection of one bin by one wavefront (writes sel/cnt).
+__device__ inline void merge_one_bin(const MergeParams &p, int64_t bin, int lane) {
   int64_t s, e;
   bin_range(p, bin, s, e);
   if (s >= e) {
@@ -118,6 +125,11 @@ __global__ __launch_bounds__(256) void k_merge(MergeParams p) {
   int64_t imn, imx;
   merged_bin(p, s, e, bin, lane, imn, imx);
   if (lane == 0) p.cnt[bin] = bin_selection(s, e, imn, imx, p.m4, p.sel + 4 * bin);
+}
+
+__global__ __launch_bounds__(256) void k_merge(MergeParams p) {
+  const int64_t bin = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (bin < p.nb) merge_one_bin(p, bin, lane_id());
 }
 
 hipError_t launch_merge(const MergeParams &p, hipStream_t st) {
@@ -147,8 +159,9 @@ hipError_t launch_binres_to_outputs(const MergeParams &p, int64_t *imin, int64_t
 
 // ------------------------------------------------------------------ compact
 
-__global__ __launch_bounds__(1024) void k_compact(CompactParams p) {
-  __shared__ int64_t lds[80];
+// Compaction by one workgroup of any size: exclusive scan of the per-bin
+// counts and the strictly increasing output (or 0..all_n-1).
+__device__ void compact_block(const CompactParams &p, int64_t *lds) {
   const int t = threadIdx.x;
   int64_t *out = p.out;
   if (p.all_n >= 0) {
@@ -177,6 +190,11 @@ __global__ __launch_bounds__(1024) void k_compact(CompactParams p) {
       *p.out_count = total;
     }
   }
+}
+
+__global__ __launch_bounds__(1024) void k_compact(CompactParams p) {
+  __shared__ int64_t lds[80];
+  compact_block(p, lds);
 }
 
 hipError_t launch_compact(const CompactParams &p, hipStream_t st) {

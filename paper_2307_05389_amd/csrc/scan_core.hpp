@@ -504,6 +504,152 @@ __device__ void scan_chunk(const ScanParams &p, int64_t c, int lane) {
   }
 }
 
+// ---- chunks classified from x (large bins) ----------------------------------
+//
+// Instead of looking its bins up in an edge array, the wavefront reads x at
+// the chunk's ends (one round trip, overlapped with the tile prefetch) and
+// maps them to bins with the edge values of the edge search: x_i lies in bin
+// b iff E_b <= x_i < E_{b+1} (the first bin also takes everything below E_1,
+// the last everything from E_{nb-1} on).  A bin boundary inside the chunk
+// (rare when bins are much longer than chunks) is found by a 64-wide search
+// of x inside the chunk, and runs of empty bins are skipped in one step.
+// The scan writes the edge array itself as a by-product: every bin start is
+// either a chunk start or a boundary found inside a chunk, so each edge is
+// written by exactly one wavefront and no separate edge search runs.
+
+// Edge values E_b = x0 + ceil(b R / nb) of int64 x, R = x_last - x0, with
+// R = q nb + r split once so that no evaluation needs a 64-bit division:
+// ceil(b R / nb) = b q + ceil(b r / nb), where b r < nb^2 < 2^62 is divided
+// by a double-precision multiply with 1/nb (off by at most one) and then
+// corrected exactly.  The values equal edge_value<int64_t>, which the edge
+// search uses.
+struct XEdges {
+  int64_t x0, nb;
+  uint64_t R, q, r;
+  double inv_nb, scale;  // 1/nb and nb/R
+  __device__ XEdges(int64_t x0_, int64_t xl, int64_t nb_) : x0(x0_), nb(nb_) {
+    R = (uint64_t)xl - (uint64_t)x0;
+    const double dnb = (double)nb, dR = (double)R;
+    inv_nb = 1.0 / dnb;
+    scale = dnb / dR;
+    // q = floor(R / nb): a double estimate (|error| < 2^13) fixed in two
+    // steps; the products wrap modulo 2^64, so only the small remainders matter
+    const double qd = dR * inv_nb;
+    int64_t qe = qd >= 18446744073709551615.0 ? (int64_t)~0ull : (int64_t)(uint64_t)qd;
+    int64_t rem = (int64_t)(R - (uint64_t)qe * (uint64_t)nb);  // |rem| < 2^45
+    qe += (int64_t)floor((double)rem * inv_nb);
+    rem = (int64_t)(R - (uint64_t)qe * (uint64_t)nb);
+    while (rem < 0) { qe--; rem += nb; }
+    while (rem >= nb) { qe++; rem -= nb; }
+    q = (uint64_t)qe;
+    r = (uint64_t)rem;
+  }
+  __device__ int64_t at(int64_t b) const {
+    const uint64_t br = (uint64_t)b * r;
+    int64_t t = (int64_t)((double)br * inv_nb);
+    int64_t rem = (int64_t)(br - (uint64_t)t * (uint64_t)nb);
+    while (rem < 0) { t--; rem += nb; }
+    while (rem >= nb) { t++; rem -= nb; }
+    return (int64_t)((uint64_t)x0 + (uint64_t)b * q + (uint64_t)t + (rem != 0 ? 1u : 0u));
+  }
+  // Bin of xi (x0 <= xi <= x_last): the largest b < nb with E_b <= xi.  Also
+  // gives E_{b+1} (`next`), the first value of a later bin (INT64_MAX with
+  // next_inf set for the last bin, which takes everything from E_{nb-1} on).
+  __device__ int64_t bin(int64_t xi, int64_t &next, bool &next_inf) const {
+    if (R == 0) {
+      next_inf = true;
+      next = INT64_MAX;
+      return nb - 1;
+    }
+    const double est = (double)((uint64_t)xi - (uint64_t)x0) * scale;
+    int64_t b = 0;
+    if (est >= 1.0) b = est >= (double)(nb - 1) ? nb - 1 : (int64_t)est;
+    int64_t eb = at(b), en = b + 1 < nb ? at(b + 1) : INT64_MAX;
+    while (b + 1 < nb && en <= xi) {
+      b++;
+      eb = en;
+      en = b + 1 < nb ? at(b + 1) : INT64_MAX;
+    }
+    while (b > 0 && eb > xi) {
+      b--;
+      en = eb;
+      eb = at(b);
+    }
+    next_inf = b + 1 >= nb;
+    next = en;
+    return b;
+  }
+};
+
+// edges[lo .. hi] = v (wave-cooperative; lo > hi writes nothing).
+__device__ inline void xc_fill(int64_t *edges, int64_t lo, int64_t hi, int64_t v, int lane) {
+  for (int64_t j = lo + lane; j <= hi; j += kWave) edges[j] = v;
+}
+
+template <typename T, int U, int NB>
+__device__ void scan_chunk_xc(const ScanParams &p, int64_t c, int lane) {
+  using C = typename Elem<T>::C;
+  constexpr int VEC = 16 / (int)sizeof(T);
+  constexpr int64_t TV = (int64_t)kWave * U;
+  const T *__restrict__ y = (const T *)p.y;
+  const int64_t *__restrict__ x = (const int64_t *)p.x;
+  const u32x4 *__restrict__ base = (const u32x4 *)(y - p.shift);
+  int64_t c0 = c * p.chunk - p.shift;
+  if (c0 < 0) c0 = 0;
+  int64_t c1 = (c + 1) * p.chunk - p.shift;
+  if (c1 > p.n) c1 = p.n;
+  if (c0 >= c1) return;
+  const int64_t vc0 = (c0 + p.shift) / VEC, vc1 = (c1 + p.shift + VEC - 1) / VEC;
+  u32x4 buf[NB][U];
+#pragma unroll
+  for (int k = 0; k < NB; k++) load_tile<U>(base, vc0 + k * TV, vc0, vc1, lane, buf[k]);
+  int npre = NB;
+  // lanes 0..5 read x[0], x[n-1], x[c0-1], x[c0], x[c1-1], x[c1]
+  const int64_t pos = lane == 0 ? 0 : lane == 1 ? p.n - 1 : lane == 2 ? c0 - 1 : lane == 3 ? c0 : lane == 4 ? c1 - 1 : c1;
+  const int64_t xv = (lane < 6 && pos >= 0 && pos < p.n) ? x[pos] : 0;
+  const int64_t nb = p.nb;
+  const XEdges E(readlane(xv, 0), readlane(xv, 1), nb);
+  const int64_t xa = readlane(xv, 2), xs = readlane(xv, 3), xe = readlane(xv, 4), xb = readlane(xv, 5);
+  int64_t n0, n1;
+  bool inf0, inf1;
+  const int64_t b0 = E.bin(xs, n0, inf0);
+  const int64_t b1 = E.bin(xe, n1, inf1);
+  // x[c0-1] <= x[c0]: it shares b0 iff it is >= E_{b0}; x[c1] >= x[c1-1]:
+  // it shares b1 iff it is below E_{b1+1}
+  int64_t bprev = -1, bnext = nb, dummy;
+  bool dinf;
+  if (c0 > 0) bprev = (b0 == 0 || xa >= E.at(b0)) ? b0 : E.bin(xa, dummy, dinf);
+  if (c1 < p.n) bnext = (inf1 || xb < n1) ? b1 : E.bin(xb, dummy, dinf);
+  xc_fill(p.xedges, bprev + 1, b0, c0, lane);  // bins starting at c0 (and empty ones before)
+  if (c1 == p.n) xc_fill(p.xedges, b1 + 1, nb, p.n, lane);
+  int64_t bin = b0, start = c0, next = n0;
+  for (;;) {
+    int64_t end = c1, nbin = 0;
+    if (bin != b1) {
+      // first index after start with x >= E_{bin+1}; it exists inside the
+      // chunk because x[c1-1] lies in a later bin
+      end = wave_lower_bound<int64_t, int64_t>(x, start + 1, c1, next, lane);
+      nbin = E.bin(x[end], next, dinf);
+      xc_fill(p.xedges, bin + 1, nbin, end, lane);  // nbin starts at end; bins between are empty
+    }
+    SegState<C> st;
+    wave_segment<T, U, NB>(base, p.shift, start, end, lane, buf, npre, st);
+    npre = 0;
+    const bool before = bin == b0 && bprev == b0, after = bin == b1 && bnext == b1;
+    if (lane == 0) write_result<T>(p, c, bin, before, after, st.vmn, st.imn, st.vmx, st.imx);
+    if (bin == b1) break;
+    bin = nbin;
+    start = end;
+  }
+}
+
+template <typename T, int U, int NB>
+__global__ __launch_bounds__(256) void k_scan_xc(ScanParams p) {
+  const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (c >= p.nchunks) return;
+  scan_chunk_xc<T, U, NB>(p, c, lane_id());
+}
+
 // ---- staged chunks (many small bins) ---------------------------------------
 //
 // The whole chunk is first copied into the wavefront's LDS slice with

@@ -114,22 +114,66 @@ def test_ties_signed_zero_and_extremes(ts, oracle_mod):
                 assert np.array_equal(gpu(ts, algo, y, n_out), orc(oracle_mod, algo, y, n_out)), (name, algo, n_out)
 
 
-@pytest.mark.parametrize("chunk,small,stage", [(4096, -1, 0), (4096, 1, 0), (65536, 100000, 0), (8192, 7, 0),
-                                               (-1, 1 << 20, 0), (8192, -1, 1), (4096, -1, 1), (32768, -1, 1),
-                                               (-1, -1, -1)])
-def test_tuning_does_not_change_results(ts, oracle_mod, chunk, small, stage):
-    """Chunk size, the one-lane-per-bin threshold and LDS staging only change
-    the work split (bins split over many chunks, many bins per wavefront,
-    bins reduced from LDS)."""
-    ts.set_tuning(chunk, small, -1, stage)
+@pytest.mark.parametrize("chunk,small,stage,xclass",
+                         [(4096, -1, 0, -1), (4096, 1, 0, -1), (65536, 100000, 0, -1), (8192, 7, 0, -1),
+                          (-1, 1 << 20, 0, -1), (8192, -1, 1, -1), (4096, -1, 1, -1), (32768, -1, 1, -1),
+                          (-1, -1, -1, -1), (4096, -1, 0, 1), (65536, 7, 0, 1), (-1, -1, 0, 0)])
+def test_tuning_does_not_change_results(ts, oracle_mod, chunk, small, stage, xclass):
+    """Chunk size, the one-lane-per-bin threshold, LDS staging and x
+    classification only change the work split (bins split over many chunks,
+    many bins per wavefront, bins reduced from LDS, bins found from x)."""
+    ts.set_tuning(chunk, small, -1, stage, xclass)
     try:
         for dtype in (np.float32, np.uint8, np.float64, np.int16):
             y = S.walk(250007, dtype, seed=5)
             x = S.timestamps(250007, 50, seed=6)
             for algo, n_out in (("minmax", 2), ("minmax", 600), ("m4", 40000), ("m4", 8)):
                 for xx in (None, x):
-                    say(f"[tuning] chunk={chunk} small={small} stage={stage} {np.dtype(dtype).name} {algo} {n_out}")
+                    say(f"[tuning] chunk={chunk} small={small} stage={stage} xclass={xclass} "
+                        f"{np.dtype(dtype).name} {algo} {n_out}")
                     assert np.array_equal(gpu(ts, algo, y, n_out, xx), orc(oracle_mod, algo, y, n_out, xx))
+    finally:
+        ts.set_tuning()
+
+
+def x_patterns(n, seed):
+    """int64 x layouts that stress finding bins from x: steady timestamps,
+    long gaps (runs of empty bins, some spanning many chunks), runs of equal
+    timestamps across chunk ends, one constant value (every point in the last
+    bin), and a range close to the whole int64 span."""
+    rng = np.random.default_rng(seed)
+    steady = S.timestamps(n, 1000, seed=seed)
+    gaps = steady.copy()
+    for k in range(1, 6):
+        gaps[k * n // 6:] += rng.integers(1, 10**9)
+    dup = np.repeat(S.timestamps((n + 4095) // 4096 * 8, 50, seed=seed + 1), 512)[:n]
+    wide = np.sort(rng.integers(np.iinfo(np.int64).min // 2 * 2 + 1, np.iinfo(np.int64).max, n, dtype=np.int64))
+    wide[0], wide[-1] = np.iinfo(np.int64).min + 1, np.iinfo(np.int64).max
+    return {"steady": steady, "gaps": gaps, "dup": dup.astype(np.int64),
+            "const": np.full(n, -123456789, np.int64), "wide": wide}
+
+
+@pytest.mark.parametrize("xclass", [1, 0])
+def test_x_classified_chunks(ts, oracle_mod, xclass):
+    """Chunks that find their bins from int64 x give the same bins (and the
+    same edge array) as the separate edge search, for any bin length: many
+    boundaries per chunk, none, and runs of empty bins."""
+    ts.set_tuning(-1, -1, -1, 0, xclass)
+    try:
+        for n in (1, 2, 4097, 300001):
+            xs = x_patterns(n, seed=n)
+            for dtype in (np.float64, np.float32, np.int16, np.uint8):
+                y = S.walk(n, dtype, seed=n + 3)
+                for name, x in xs.items():
+                    for algo, n_out in (("m4", 4), ("m4", 40), ("minmax", 1000), ("m4", 4000), ("minmax", 2 * n + 2)):
+                        say(f"[xclass={xclass}] n={n} {np.dtype(dtype).name} x={name} {algo} {n_out}")
+                        assert np.array_equal(gpu(ts, algo, y, n_out, x), orc(oracle_mod, algo, y, n_out, x)), \
+                            (n, name, algo, n_out)
+                if n > 2:
+                    for name in ("gaps", "dup"):
+                        say(f"[xclass={xclass}] n={n} {np.dtype(dtype).name} x={name} minmaxlttb")
+                        got = gpu(ts, "minmaxlttb", y, 200, xs[name], 4)
+                        assert np.array_equal(got, orc(oracle_mod, "minmaxlttb", y, 200, xs[name], 4)), (n, name)
     finally:
         ts.set_tuning()
 
