@@ -86,28 +86,49 @@ static int32_t g_xclass_override = -1;
 // of kStageChunk bytes (one HBM round trip per chunk instead of one per bin).
 static const int64_t kStageBin = 4096, kStageChunk = 8192;
 
+// Shapes of the scan that classifies chunks from int64 x (sweeps on MI355X
+// over 1e8-point series): its per-chunk set-up costs more than the edge
+// lookup, so narrow types take longer chunks.
+static ScanShape xclass_shape(int ydt) {
+  switch (elem_size(ydt)) {
+    case 1: return {1, 32768, 0, 1};
+    case 2: return {1, 65536, 0, 1};
+    case 4: return {0, 32768, 0, 1};
+    default: return {2, 32768, 0, 1};
+  }
+}
+
+// Halves the chunk (down to 4 KB) until the series has min_chunks chunks.
+static int64_t fit_chunk(int64_t chunk_bytes, int64_t total, int64_t min_chunks) {
+  while (chunk_bytes > 4096 && total / chunk_bytes < min_chunks) chunk_bytes /= 2;
+  return chunk_bytes;
+}
+
 // Bins averaging at least kXclassChunks chunks are classified from int64 x
 // by the scan itself (the edge search would otherwise be a separate pass).
 static const int64_t kXclassChunks = 2;
 
 static ScanShape scan_shape(int ydt, int xdt, int64_t n, int64_t nb) {
+  const int64_t total = n * (int64_t)elem_size(ydt);
+  const int32_t stage = g_stage_override >= 0 ? g_stage_override : (nb > 0 && n / nb < kStageBin ? 1 : 0);
+  if (xdt == TS_I64 && !stage && g_xclass_override != 0) {
+    ScanShape sh = xclass_shape(ydt);
+    if (g_variant_override >= 0) sh.variant = g_variant_override;
+    sh.chunk_bytes = g_chunk_bytes_override > 0 ? g_chunk_bytes_override : fit_chunk(sh.chunk_bytes, total, 2048);
+    const int64_t ce = sh.chunk_bytes / (int64_t)elem_size(ydt);
+    if (g_xclass_override == 1 || (nb > 0 && n / nb >= kXclassChunks * ce)) return sh;
+  }
   ScanShape sh = default_shape(ydt);
   if (g_variant_override >= 0) sh.variant = g_variant_override;
-  sh.stage = g_stage_override >= 0 ? g_stage_override : (nb > 0 && n / nb < kStageBin ? 1 : 0);
+  sh.stage = stage;
   if (g_chunk_bytes_override > 0) {
     sh.chunk_bytes = g_chunk_bytes_override;
   } else if (sh.stage) {
     sh.chunk_bytes = kStageChunk;
   } else {
-    const int64_t total = n * (int64_t)elem_size(ydt);
-    while (sh.chunk_bytes > 4096 && total / sh.chunk_bytes < 4096) sh.chunk_bytes /= 2;
+    sh.chunk_bytes = fit_chunk(sh.chunk_bytes, total, 4096);
   }
   if (sh.stage && sh.chunk_bytes > 32768) sh.chunk_bytes = 32768;  // LDS per workgroup
-  sh.xclass = 0;
-  if (xdt == TS_I64 && !sh.stage) {
-    const int64_t ce = sh.chunk_bytes / (int64_t)elem_size(ydt);
-    sh.xclass = g_xclass_override >= 0 ? g_xclass_override : (nb > 0 && n / nb >= kXclassChunks * ce ? 1 : 0);
-  }
   return sh;
 }
 

@@ -586,6 +586,30 @@ __device__ inline void xc_fill(int64_t *edges, int64_t lo, int64_t hi, int64_t v
   for (int64_t j = lo + lane; j <= hi; j += kWave) edges[j] = v;
 }
 
+// First index i in (start, c1) with x[i] >= v, given x[start] = xs < v <=
+// x[c1-1] = xe.  Timestamps are close to evenly spaced, so a linear
+// interpolation usually lands within a 64-element window holding the answer
+// (one or two cache lines); otherwise the window narrows the range for the
+// 64-ary search.
+__device__ inline int64_t xc_boundary(const int64_t *__restrict__ x, int64_t start, int64_t c1, int64_t xs,
+                                      int64_t xe, int64_t v, int lane) {
+  int64_t lo = start + 1, hi = c1;
+  const double f = (double)((uint64_t)v - (uint64_t)xs) / (double)((uint64_t)xe - (uint64_t)xs);
+  int64_t w0 = start + (int64_t)(f * (double)(c1 - 1 - start)) - 32;
+  if (w0 > hi - kWave) w0 = hi - kWave;
+  if (w0 < lo) w0 = lo;
+  const int64_t q = w0 + lane;
+  const uint64_t m = ballot(q < hi && x[q] >= v);
+  if (m) {
+    const int first = __builtin_ctzll(m);
+    if (first > 0 || w0 == lo) return w0 + first;
+    hi = w0 + 1;  // x[w0] >= v already
+  } else {
+    lo = w0 + kWave < hi ? w0 + kWave : hi;
+  }
+  return wave_lower_bound<int64_t, int64_t>(x, lo, hi, v, lane);
+}
+
 template <typename T, int U, int NB>
 __device__ void scan_chunk_xc(const ScanParams &p, int64_t c, int lane) {
   using C = typename Elem<T>::C;
@@ -622,14 +646,15 @@ __device__ void scan_chunk_xc(const ScanParams &p, int64_t c, int lane) {
   if (c1 < p.n) bnext = (inf1 || xb < n1) ? b1 : E.bin(xb, dummy, dinf);
   xc_fill(p.xedges, bprev + 1, b0, c0, lane);  // bins starting at c0 (and empty ones before)
   if (c1 == p.n) xc_fill(p.xedges, b1 + 1, nb, p.n, lane);
-  int64_t bin = b0, start = c0, next = n0;
+  int64_t bin = b0, start = c0, next = n0, xstart = xs;
   for (;;) {
     int64_t end = c1, nbin = 0;
     if (bin != b1) {
       // first index after start with x >= E_{bin+1}; it exists inside the
       // chunk because x[c1-1] lies in a later bin
-      end = wave_lower_bound<int64_t, int64_t>(x, start + 1, c1, next, lane);
-      nbin = E.bin(x[end], next, dinf);
+      end = xc_boundary(x, start, c1, xstart, xe, next, lane);
+      xstart = x[end];
+      nbin = E.bin(xstart, next, dinf);
       xc_fill(p.xedges, bin + 1, nbin, end, lane);  // nbin starts at end; bins between are empty
     }
     SegState<C> st;
