@@ -68,11 +68,11 @@ struct ScanShape {
 
 static ScanShape default_shape(int ydt) {
   switch (ydt) {
-    case TS_U8: return {3, 16384, 0, 0};
-    case TS_I8: return {0, 65536, 0, 0};
+    case TS_U8: return {1, 16384, 0, 0};
+    case TS_I8: return {1, 16384, 0, 0};
     case TS_I16: case TS_U16: case TS_F16: return {0, 16384, 0, 0};
     case TS_I32: case TS_U32: case TS_F32: return {2, 16384, 0, 0};
-    default: return {2, 32768, 0, 0};
+    default: return {2, 16384, 0, 0};
   }
 }
 
@@ -93,8 +93,8 @@ static ScanShape xclass_shape(int ydt) {
   switch (elem_size(ydt)) {
     case 1: return {1, 32768, 0, 1};
     case 2: return {1, 65536, 0, 1};
-    case 4: return {0, 32768, 0, 1};
-    default: return {2, 32768, 0, 1};
+    case 4: return {0, 16384, 0, 1};
+    default: return {2, 16384, 0, 1};
   }
 }
 

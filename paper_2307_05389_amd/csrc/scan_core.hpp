@@ -541,8 +541,10 @@ struct XEdges {
     rem = (int64_t)(R - (uint64_t)qe * (uint64_t)nb);
     while (rem < 0) { qe--; rem += nb; }
     while (rem >= nb) { qe++; rem -= nb; }
-    q = (uint64_t)qe;
-    r = (uint64_t)rem;
+    q = uniform((uint64_t)qe);
+    r = uniform((uint64_t)rem);
+    inv_nb = uniform(inv_nb);
+    scale = uniform(scale);
   }
   __device__ int64_t at(int64_t b) const {
     const uint64_t br = (uint64_t)b * r;
@@ -550,7 +552,7 @@ struct XEdges {
     int64_t rem = (int64_t)(br - (uint64_t)t * (uint64_t)nb);
     while (rem < 0) { t--; rem += nb; }
     while (rem >= nb) { t++; rem -= nb; }
-    return (int64_t)((uint64_t)x0 + (uint64_t)b * q + (uint64_t)t + (rem != 0 ? 1u : 0u));
+    return uniform((int64_t)((uint64_t)x0 + (uint64_t)b * q + (uint64_t)t + (rem != 0 ? 1u : 0u)));
   }
   // Bin of xi (x0 <= xi <= x_last): the largest b < nb with E_b <= xi.  Also
   // gives E_{b+1} (`next`), the first value of a later bin (INT64_MAX with
@@ -575,8 +577,9 @@ struct XEdges {
       en = eb;
       eb = at(b);
     }
+    b = uniform(b);
     next_inf = b + 1 >= nb;
-    next = en;
+    next = uniform(en);
     return b;
   }
 };
@@ -670,7 +673,7 @@ __device__ void scan_chunk_xc(const ScanParams &p, int64_t c, int lane) {
 
 template <typename T, int U, int NB>
 __global__ __launch_bounds__(256) void k_scan_xc(ScanParams p) {
-  const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t c = uniform((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6));
   if (c >= p.nchunks) return;
   scan_chunk_xc<T, U, NB>(p, c, lane_id());
 }
@@ -780,7 +783,7 @@ __host__ __device__ inline int64_t staged_lds_vectors(int64_t chunk_elems, int v
 template <typename T>
 __global__ __launch_bounds__(256) void k_scan_staged(ScanParams p) {
   extern __shared__ u32x4 stage_lds[];
-  const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t c = uniform((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6));
   if (c >= p.nchunks) return;
   constexpr int VEC = 16 / (int)sizeof(T);
   const int64_t per = staged_lds_vectors(p.chunk, VEC);
@@ -789,7 +792,7 @@ __global__ __launch_bounds__(256) void k_scan_staged(ScanParams p) {
 
 template <typename T, int U, int NB>
 __global__ __launch_bounds__(256) void k_scan(ScanParams p) {
-  const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t c = uniform((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6));
   if (c >= p.nchunks) return;
   scan_chunk<T, U, NB>(p, c, lane_id());
 }
