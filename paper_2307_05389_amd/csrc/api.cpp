@@ -141,7 +141,7 @@ static int32_t small_threshold() { return g_small_override > 0 ? g_small_overrid
 struct ScanPlan {
   int64_t nb = 0, chunk = 0, nchunks = 0;
   int32_t variant = 0, stage = 0, xclass = 0;
-  size_t off_edges = 0, off_binres = 0, off_partL = 0, off_partR = 0, off_sel = 0, off_cnt = 0,
+  size_t off_edges = 0, off_binres = 0, off_partL = 0, off_partR = 0, off_sel = 0, off_cnt = 0, off_bsum = 0,
          bytes = 0;
 };
 
@@ -172,6 +172,8 @@ static ScanPlan scan_plan(int ydt, int xdt, int64_t n, int64_t nb, size_t base) 
   o = align256(o + sizeof(int64_t) * 4 * (size_t)nb);
   p.off_cnt = o;
   o = align256(o + sizeof(int64_t) * (size_t)nb);
+  p.off_bsum = o;
+  if (nb > kCompactSingleMax) o = align256(o + sizeof(int64_t) * (size_t)compact_blocks(nb));
   p.bytes = o;
   return p;
 }
@@ -323,6 +325,7 @@ static int run_scan(const ts_series &s, int64_t nb, int m4, const ScanPlan &pl, 
   cp.index_offset = index_offset;
   cp.endpoints_n = endpoints_n;
   cp.all_n = -1;
+  cp.bsum = nb > kCompactSingleMax ? (int64_t *)wsp(ws, pl.off_bsum) : nullptr;
   if ((e = launch_merge(mp, st)) != hipSuccess) return hip_fail(e, "merge");
   if ((e = launch_compact(cp, st)) != hipSuccess) return hip_fail(e, "compact");
   return TS_OK;

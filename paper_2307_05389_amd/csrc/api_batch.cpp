@@ -83,7 +83,6 @@ size_t batch_layout(ts_plan *p, int64_t chunk_bytes) {
         t.n = s.n - 2;
       }
     }
-    t.slot_begin = p->total_slots;
     int grp = 0;
     if (t.mode == 0) {
       const int64_t es = (int64_t)esize(t.ydt);
@@ -117,7 +116,6 @@ size_t batch_layout(ts_plan *p, int64_t chunk_bytes) {
       p->group_total[grp] += t.nchunks;
       p->total_chunks += t.nchunks;
       p->total_slots += t.nb + 1;
-      for (int64_t k = 0; k < t.nb + 1; k++) p->slot_task.push_back((int32_t)ti);
     }
     if (in.algo == TS_MINMAXLTTB && t.mode != 1) {
       t.m_max = t.mode == 0 ? in.n_out * in.minmax_ratio + 2 : s.n;
@@ -140,6 +138,22 @@ size_t batch_layout(ts_plan *p, int64_t chunk_bytes) {
     if (in.algo == TS_MINMAXLTTB) p->lttb_tasks.push_back((int32_t)ti);
     p->tasks.push_back(t);
     ti++;
+  }
+  // Bin slots: tasks whose bins span many chunks first (a wavefront merges
+  // each of their bins), then the rest (a thread per bin).
+  p->wave_slots = 0;
+  int64_t next = 0;
+  for (int pass = 0; pass < 2; pass++) {
+    for (size_t k = 0; k < p->tasks.size(); k++) {
+      BatchTask &t = p->tasks[k];
+      if (t.mode != 0) continue;
+      const bool lanes = t.stage || t.n / t.nb <= kLaneMergeChunks * t.chunk;
+      if (lanes != (pass == 1)) continue;
+      t.slot_begin = next;
+      next += t.nb + 1;
+      for (int64_t b = 0; b < t.nb + 1; b++) p->slot_task.push_back((int32_t)k);
+    }
+    if (pass == 0) p->wave_slots = next;
   }
   return o;
 }
@@ -200,6 +214,7 @@ BatchArgs args(const ts_plan *p, const void *d_table, int64_t *out, int64_t *cou
   a.ntasks = (int64_t)p->tasks.size();
   a.total_chunks = p->total_chunks;
   a.total_slots = p->total_slots;
+  a.wave_slots = p->wave_slots;
   a.n_lttb = (int64_t)p->lttb_tasks.size();
   a.ws = (char *)ws;
   a.out = out;

@@ -123,20 +123,20 @@ __device__ int64_t group_pos_of_item(const int64_t *__restrict__ cb, int64_t nta
 // only the item index lives across iterations: carrying the task's
 // parameters through the loop would push wave-uniform state out of scalar
 // registers and double the vector registers per wavefront.
-template <typename T>
+template <typename T, int U, int NB>
 __global__ __launch_bounds__(256) void k_batch_scan(const BatchTask *__restrict__ tasks, const int64_t *__restrict__ cb,
                                                     const int32_t *__restrict__ tix, int64_t ntasks, int64_t total,
                                                     char *ws, int32_t small) {
   const int lane = lane_id();
   const int64_t W = (int64_t)gridDim.x * 4;
-  const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t w = uniform((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6));
   const int64_t i0 = total * w / W, i1 = total * (w + 1) / W;
 #pragma nounroll
   for (int64_t item = i0; item < i1; item++) {
     const int64_t k = uniform(group_pos_of_item(cb, ntasks, item, lane));
     const BatchTask *tk = tasks + uniform(tix[k]);
     const ScanParams sp = task_scan_params_uniform(ws, tk, small);
-    scan_chunk<T, 2, 2>(sp, item - uniform(tk->chunk_begin), lane);
+    scan_chunk<T, U, NB>(sp, item - uniform(tk->chunk_begin), lane);
   }
 }
 
@@ -149,7 +149,7 @@ __global__ __launch_bounds__(256) void k_batch_scan_staged(const BatchTask *__re
   extern __shared__ u32x4 stage_lds[];
   const int lane = lane_id();
   const int64_t W = (int64_t)gridDim.x * 4;
-  const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t w = uniform((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6));
   const int64_t i0 = total * w / W, i1 = total * (w + 1) / W;
   u32x4 *lds = stage_lds + (threadIdx.x >> 6) * lds_per;
 #pragma nounroll
@@ -190,18 +190,20 @@ hipError_t launch_batch_scan(const BatchArgs &a, const BatchGroup &g, int64_t gr
     return hipGetLastError();
   }
 #define TSDS_BATCH_ARGS a.tasks, g.cb, g.tix, g.ntasks, g.total, a.ws, a.small
+  // tile shapes per element size as in the single-series scan (bytes: 4x1,
+  // 16-bit: 4x2, 32/64-bit: 8x1 vectors per lane x tiles in flight)
   switch (g.ydt) {
-    case TS_I8: k_batch_scan<int8_t><<<grid, block, 0, st>>>(TSDS_BATCH_ARGS); break;
-    case TS_I16: k_batch_scan<int16_t><<<grid, block, 0, st>>>(TSDS_BATCH_ARGS); break;
-    case TS_I32: k_batch_scan<int32_t><<<grid, block, 0, st>>>(TSDS_BATCH_ARGS); break;
-    case TS_I64: k_batch_scan<int64_t><<<grid, block, 0, st>>>(TSDS_BATCH_ARGS); break;
-    case TS_U8: k_batch_scan<uint8_t><<<grid, block, 0, st>>>(TSDS_BATCH_ARGS); break;
-    case TS_U16: k_batch_scan<uint16_t><<<grid, block, 0, st>>>(TSDS_BATCH_ARGS); break;
-    case TS_U32: k_batch_scan<uint32_t><<<grid, block, 0, st>>>(TSDS_BATCH_ARGS); break;
-    case TS_U64: k_batch_scan<uint64_t><<<grid, block, 0, st>>>(TSDS_BATCH_ARGS); break;
-    case TS_F16: k_batch_scan<half_t><<<grid, block, 0, st>>>(TSDS_BATCH_ARGS); break;
-    case TS_F32: k_batch_scan<float><<<grid, block, 0, st>>>(TSDS_BATCH_ARGS); break;
-    case TS_F64: k_batch_scan<double><<<grid, block, 0, st>>>(TSDS_BATCH_ARGS); break;
+    case TS_I8: k_batch_scan<int8_t, 4, 1><<<grid, block, 0, st>>>(TSDS_BATCH_ARGS); break;
+    case TS_I16: k_batch_scan<int16_t, 4, 2><<<grid, block, 0, st>>>(TSDS_BATCH_ARGS); break;
+    case TS_I32: k_batch_scan<int32_t, 8, 1><<<grid, block, 0, st>>>(TSDS_BATCH_ARGS); break;
+    case TS_I64: k_batch_scan<int64_t, 8, 1><<<grid, block, 0, st>>>(TSDS_BATCH_ARGS); break;
+    case TS_U8: k_batch_scan<uint8_t, 4, 1><<<grid, block, 0, st>>>(TSDS_BATCH_ARGS); break;
+    case TS_U16: k_batch_scan<uint16_t, 4, 2><<<grid, block, 0, st>>>(TSDS_BATCH_ARGS); break;
+    case TS_U32: k_batch_scan<uint32_t, 8, 1><<<grid, block, 0, st>>>(TSDS_BATCH_ARGS); break;
+    case TS_U64: k_batch_scan<uint64_t, 8, 1><<<grid, block, 0, st>>>(TSDS_BATCH_ARGS); break;
+    case TS_F16: k_batch_scan<half_t, 4, 2><<<grid, block, 0, st>>>(TSDS_BATCH_ARGS); break;
+    case TS_F32: k_batch_scan<float, 8, 1><<<grid, block, 0, st>>>(TSDS_BATCH_ARGS); break;
+    case TS_F64: k_batch_scan<double, 8, 1><<<grid, block, 0, st>>>(TSDS_BATCH_ARGS); break;
     default: return hipErrorInvalidValue;
   }
 #undef TSDS_BATCH_ARGS
@@ -224,10 +226,13 @@ __device__ inline MergeParams task_merge_params(const BatchArgs &a, const BatchT
   return mp;
 }
 
+// Slots [0, wave_slots) belong to tasks whose bins span many chunks: one
+// wavefront per slot.  The rest (bins spanning few chunks): one thread per
+// slot, in k_batch_merge_lanes.
 __global__ __launch_bounds__(256) void k_batch_merge(BatchArgs a) {
   const int lane = lane_id();
   const int64_t slot = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (slot >= a.total_slots) return;
+  if (slot >= a.wave_slots) return;
   const BatchTask &t = a.tasks[a.slot_task[slot]];
   const int64_t bin = slot - t.slot_begin;
   if (t.mode != 0 || bin >= t.nb) return;
@@ -243,9 +248,28 @@ __global__ __launch_bounds__(256) void k_batch_merge(BatchArgs a) {
   if (lane == 0) mp.cnt[bin] = bin_selection(s, e, imn, imx, mp.m4, mp.sel + 4 * bin);
 }
 
+__global__ __launch_bounds__(256) void k_batch_merge_lanes(BatchArgs a) {
+  const int64_t slot = a.wave_slots + (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (slot >= a.total_slots) return;
+  const BatchTask &t = a.tasks[a.slot_task[slot]];
+  const int64_t bin = slot - t.slot_begin;
+  if (t.mode != 0 || bin >= t.nb) return;
+  const MergeParams mp = task_merge_params(a, t);
+  int64_t s, e;
+  bin_range(mp, bin, s, e);
+  if (s >= e) {
+    mp.cnt[bin] = 0;
+    return;
+  }
+  int64_t imn, imx;
+  merged_bin_lane(mp, s, e, bin, imn, imx);
+  mp.cnt[bin] = bin_selection(s, e, imn, imx, mp.m4, mp.sel + 4 * bin);
+}
+
 hipError_t launch_batch_merge(const BatchArgs &a, hipStream_t st) {
-  if (a.total_slots == 0) return hipSuccess;
-  k_batch_merge<<<dim3((unsigned)((a.total_slots + 3) / 4)), dim3(256), 0, st>>>(a);
+  if (a.wave_slots > 0) k_batch_merge<<<dim3((unsigned)((a.wave_slots + 3) / 4)), dim3(256), 0, st>>>(a);
+  const int64_t lanes = a.total_slots - a.wave_slots;
+  if (lanes > 0) k_batch_merge_lanes<<<dim3((unsigned)((lanes + 255) / 256)), dim3(256), 0, st>>>(a);
   return hipGetLastError();
 }
 

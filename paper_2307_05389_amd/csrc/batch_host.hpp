@@ -15,6 +15,7 @@ struct ts_plan {
   std::vector<tsds::BatchTask> tasks;
   std::vector<int32_t> slot_task, lttb_tasks;
   int64_t total_chunks = 0, total_slots = 0;
+  int64_t wave_slots = 0;   // slots of tasks merged a wavefront per bin come first
   // per (element type, staged): task list and first work items; group
   // g = dtype + 11 * staged
   std::vector<int64_t> group_cb[22];

@@ -47,6 +47,10 @@ struct MergeParams {
   int64_t *cnt;           // [nb]   how many
 };
 
+// The merge takes a bin per thread while bins average at most this many
+// chunks, a wavefront per bin above.
+constexpr int64_t kLaneMergeChunks = 4;
+
 struct CompactParams {
   int64_t nb;
   const int64_t *sel;
@@ -56,7 +60,14 @@ struct CompactParams {
   int64_t index_offset;   // added to every index (interior preselection)
   int64_t endpoints_n;    // > 0: also write out[-1] = 0 and out[count] = endpoints_n - 1
   int64_t all_n;          // >= 0: ignore bins, write out[i] = i for i < all_n
+  int64_t *bsum;          // [compact_blocks(nb)] scratch of the multi-workgroup compaction (NULL: one workgroup)
 };
+
+// Bins per workgroup of the multi-workgroup compaction, and the bin count
+// from which it is used (below it one workgroup scans every bin).
+constexpr int64_t kCompactBins = 4096;
+constexpr int64_t kCompactSingleMax = 65536;
+inline int64_t compact_blocks(int64_t nb) { return (nb + kCompactBins - 1) / kCompactBins; }
 
 size_t elem_size(int dtype);
 int vec_width(int dtype);
@@ -127,6 +138,7 @@ struct BatchArgs {
   const int32_t *slot_task;  // [total_slots] task of each global bin slot
   const int32_t *lttb_tasks; // [n_lttb] indices of MinMaxLTTB tasks
   int64_t ntasks, total_chunks, total_slots, n_lttb;
+  int64_t wave_slots;        // slots [0, wave_slots): tasks merged a wavefront per bin
   char *ws;
   int64_t *out;
   int64_t *counts;

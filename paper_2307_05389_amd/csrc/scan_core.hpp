@@ -83,20 +83,60 @@ __device__ int64_t edge_start(const X *x, int64_t n, int64_t nb, int64_t b, int 
 
 // ------------------------------------------------------------------ scan
 
-// Start of bin b (b <= nb); b >= nb gives the end of the last bin.
-__device__ inline int64_t edge_at(const int64_t *edges, int64_t n, int64_t nb, int64_t b) {
+// ceil(b N / nb) for 0 <= b <= nb < 2^31 without a 64-bit division (a long
+// instruction sequence on this GPU): N = q nb + r is split once, with q from
+// a double-precision estimate corrected exactly; b r < nb^2 < 2^62 is then
+// divided by a double multiply with 1/nb (off by at most one) and corrected
+// exactly.  Products wrap modulo 2^64, so only the small remainders matter.
+struct CeilMulDiv {
+  uint64_t q, r;
+  int64_t nb;
+  double inv_nb;
+  __device__ CeilMulDiv(uint64_t N, int64_t nb_) : nb(nb_) {
+    inv_nb = 1.0 / (double)nb;
+    const double qd = (double)N * inv_nb;  // |error| < 2^13
+    int64_t qe = qd >= 18446744073709551615.0 ? (int64_t)~0ull : (int64_t)(uint64_t)qd;
+    int64_t rem = (int64_t)(N - (uint64_t)qe * (uint64_t)nb);  // |rem| < 2^45
+    qe += (int64_t)floor((double)rem * inv_nb);
+    rem = (int64_t)(N - (uint64_t)qe * (uint64_t)nb);
+    while (rem < 0) { qe--; rem += nb; }
+    while (rem >= nb) { qe++; rem -= nb; }
+    q = (uint64_t)qe;
+    r = (uint64_t)rem;
+  }
+  __device__ uint64_t at(int64_t b) const {
+    const uint64_t br = (uint64_t)b * r;
+    int64_t t = (int64_t)((double)br * inv_nb);
+    int64_t rem = (int64_t)(br - (uint64_t)t * (uint64_t)nb);
+    while (rem < 0) { t--; rem += nb; }
+    while (rem >= nb) { t++; rem -= nb; }
+    return (uint64_t)b * q + (uint64_t)t + (rem != 0 ? 1u : 0u);
+  }
+};
+
+// Closed-form bins of a series without x: bin b starts at ceil(b (n-1) / nb).
+__device__ inline CeilMulDiv closed_bins(int64_t n, int64_t nb) { return CeilMulDiv(n > 0 ? (uint64_t)(n - 1) : 0u, nb); }
+
+// Start of bin b (b <= nb); b >= nb gives the end of the last bin.  `cm` is
+// closed_bins(n, nb) (used only when edges is NULL).
+__device__ inline int64_t edge_at(const int64_t *edges, const CeilMulDiv &cm, int64_t n, int64_t nb, int64_t b) {
   if (b >= nb) return edges ? edges[nb] : n;
   if (edges) return edges[b];
-  uint64_t num = (uint64_t)b * (uint64_t)(n - 1);
-  return (int64_t)((num + (uint64_t)nb - 1) / (uint64_t)nb);
+  return (int64_t)cm.at(b);
 }
 
 // First bin whose range can intersect [c0, ...): the last b with start <= c0.
-__device__ int64_t first_bin(const int64_t *edges, int64_t n, int64_t nb, int64_t c0, int lane) {
+__device__ int64_t first_bin(const int64_t *edges, const CeilMulDiv &cm, int64_t n, int64_t nb, int64_t c0,
+                             int lane) {
   if (!edges) {
     if (n <= 1) return 0;
-    uint64_t q = (uint64_t)c0 * (uint64_t)nb / (uint64_t)(n - 1);
-    return q < (uint64_t)nb ? (int64_t)q : nb - 1;
+    // start(b) <= c0  <=>  b <= c0 nb / (n-1): estimate, then correct exactly
+    const double est = (double)c0 * (double)nb / (double)(n - 1);
+    int64_t b = 0;
+    if (est >= 1.0) b = est >= (double)(nb - 1) ? nb - 1 : (int64_t)est;
+    while (b + 1 < nb && (int64_t)cm.at(b + 1) <= c0) b++;
+    while (b > 0 && (int64_t)cm.at(b) > c0) b--;
+    return b;
   }
   if (edges[0] > c0) return 0;
   int64_t lo = 0, hi = nb;  // edges[lo] <= c0; the answer is < hi
@@ -466,12 +506,13 @@ __device__ void scan_chunk(const ScanParams &p, int64_t c, int lane) {
   for (int k = 0; k < NB; k++) load_tile<U>(base, vc0 + k * TV, vc0, vc1, lane, buf[k]);
   int npre = NB;
 
-  int64_t b = first_bin(p.edges, p.n, p.nb, c0, lane);
+  const CeilMulDiv cm = closed_bins(p.n, p.nb);
+  int64_t b = uniform(first_bin(p.edges, cm, p.n, p.nb, c0, lane));
   for (;;) {
     const int64_t bb = b + lane;
     const bool inb = bb < p.nb;
-    const int64_t s = edge_at(p.edges, p.n, p.nb, bb);
-    const int64_t e = edge_at(p.edges, p.n, p.nb, bb + 1);
+    const int64_t s = edge_at(p.edges, cm, p.n, p.nb, bb);
+    const int64_t e = edge_at(p.edges, cm, p.n, p.nb, bb + 1);
     const int64_t lo = s > c0 ? s : c0;
     const int64_t hi = e < c1 ? e : c1;
     const bool valid = inb && lo < hi;
@@ -525,35 +566,17 @@ __device__ void scan_chunk(const ScanParams &p, int64_t c, int lane) {
 // search uses.
 struct XEdges {
   int64_t x0, nb;
-  uint64_t R, q, r;
-  double inv_nb, scale;  // 1/nb and nb/R
-  __device__ XEdges(int64_t x0_, int64_t xl, int64_t nb_) : x0(x0_), nb(nb_) {
-    R = (uint64_t)xl - (uint64_t)x0;
-    const double dnb = (double)nb, dR = (double)R;
-    inv_nb = 1.0 / dnb;
-    scale = dnb / dR;
-    // q = floor(R / nb): a double estimate (|error| < 2^13) fixed in two
-    // steps; the products wrap modulo 2^64, so only the small remainders matter
-    const double qd = dR * inv_nb;
-    int64_t qe = qd >= 18446744073709551615.0 ? (int64_t)~0ull : (int64_t)(uint64_t)qd;
-    int64_t rem = (int64_t)(R - (uint64_t)qe * (uint64_t)nb);  // |rem| < 2^45
-    qe += (int64_t)floor((double)rem * inv_nb);
-    rem = (int64_t)(R - (uint64_t)qe * (uint64_t)nb);
-    while (rem < 0) { qe--; rem += nb; }
-    while (rem >= nb) { qe++; rem -= nb; }
-    q = uniform((uint64_t)qe);
-    r = uniform((uint64_t)rem);
-    inv_nb = uniform(inv_nb);
-    scale = uniform(scale);
+  uint64_t R;
+  CeilMulDiv cm;
+  double scale;  // nb / R
+  __device__ XEdges(int64_t x0_, int64_t xl, int64_t nb_)
+      : x0(x0_), nb(nb_), R((uint64_t)xl - (uint64_t)x0_), cm((uint64_t)xl - (uint64_t)x0_, nb_) {
+    scale = uniform((double)nb / (double)R);
+    cm.q = uniform(cm.q);
+    cm.r = uniform(cm.r);
+    cm.inv_nb = uniform(cm.inv_nb);
   }
-  __device__ int64_t at(int64_t b) const {
-    const uint64_t br = (uint64_t)b * r;
-    int64_t t = (int64_t)((double)br * inv_nb);
-    int64_t rem = (int64_t)(br - (uint64_t)t * (uint64_t)nb);
-    while (rem < 0) { t--; rem += nb; }
-    while (rem >= nb) { t++; rem -= nb; }
-    return uniform((int64_t)((uint64_t)x0 + (uint64_t)b * q + (uint64_t)t + (rem != 0 ? 1u : 0u)));
-  }
+  __device__ int64_t at(int64_t b) const { return uniform((int64_t)((uint64_t)x0 + cm.at(b))); }
   // Bin of xi (x0 <= xi <= x_last): the largest b < nb with E_b <= xi.  Also
   // gives E_{b+1} (`next`), the first value of a later bin (INT64_MAX with
   // next_inf set for the last bin, which takes everything from E_{nb-1} on).
@@ -687,7 +710,93 @@ __global__ __launch_bounds__(256) void k_scan_xc(ScanParams p) {
 // wavefront for longer ones.  A chunk holding hundreds of bins thus costs one
 // HBM round trip instead of one per bin.  `lds` holds chunk/VEC + 1 vectors.
 
-constexpr int64_t kStageLane = 512;
+constexpr int64_t kStageLane = 64;
+
+// Lexicographic (value, offset) minimum and maximum inside aligned groups of
+// G lanes (4 or 16): xor 1 and xor 2 inside quads, then the half-row mirror
+// (the other quad of 8) and the row mirror (the other 8 of 16).  Equal values
+// keep the smaller offset, so the result is the group's first occurrence.
+template <int CTRL, typename C>
+__device__ inline void lex_step(C &vmn, int32_t &jmn, C &vmx, int32_t &jmx) {
+  const C omn = dpp_any<CTRL, 0xf>(vmn), omx = dpp_any<CTRL, 0xf>(vmx);
+  const int32_t pmn = (int32_t)dpp32<CTRL, 0xf>((uint32_t)jmn), pmx = (int32_t)dpp32<CTRL, 0xf>((uint32_t)jmx);
+  if (omn < vmn || (omn == vmn && pmn < jmn)) { vmn = omn; jmn = pmn; }
+  if (vmx < omx || (omx == vmx && pmx < jmx)) { vmx = omx; jmx = pmx; }
+}
+
+template <int G, typename C>
+__device__ inline void group_lex(C &vmn, int32_t &jmn, C &vmx, int32_t &jmx) {
+  lex_step<0xB1>(vmn, jmn, vmx, jmx);    // quad_perm [1,0,3,2]
+  lex_step<0x4E>(vmn, jmn, vmx, jmx);    // quad_perm [2,3,0,1]
+  if constexpr (G >= 16) {
+    lex_step<0x141>(vmn, jmn, vmx, jmx);  // row_half_mirror
+    lex_step<0x140>(vmn, jmn, vmx, jmx);  // row_mirror
+  }
+}
+
+// One round of a staged chunk with G lanes per bin (G = 1, 4 or 16): lane l
+// takes bin b + l / G and, inside the chunk, its elements l % G, l % G + G,
+// ... in index order; the group then reduces (value, offset) pairs.  Returns
+// false after the round that reaches the chunk's end.
+template <typename T, int G>
+__device__ inline bool staged_round(const ScanParams &p, const CeilMulDiv &cm, int64_t c, int64_t c0, int64_t c1,
+                                    const T *lt, int64_t g_base, int64_t &b, int lane) {
+  using E = Elem<T>;
+  using C = typename E::C;
+  const int sub = lane % G;
+  const int64_t bb = b + lane / G;
+  const bool inb = bb < p.nb;
+  const int64_t s = edge_at(p.edges, cm, p.n, p.nb, bb);
+  const int64_t e = edge_at(p.edges, cm, p.n, p.nb, bb + 1);
+  const int64_t lo = s > c0 ? s : c0;
+  const int64_t hi = e < c1 ? e : c1;
+  const bool valid = inb && lo < hi;
+  C vmn = E::highest(), vmx = E::lowest();
+  int32_t jmn = INT32_MAX, jmx = INT32_MAX;
+  if (valid) {
+    const int32_t o1 = (int32_t)(hi - g_base);
+    int32_t j = (int32_t)(lo - g_base) + sub;
+    for (; j + 3 * G < o1; j += 4 * G) {  // four LDS reads in flight
+      C v[4];
+#pragma unroll
+      for (int u = 0; u < 4; u++) v[u] = E::load(lt + j + u * G);
+#pragma unroll
+      for (int u = 0; u < 4; u++) {
+        if (jmn == INT32_MAX || v[u] < vmn) { vmn = v[u]; jmn = j + u * G; }
+        if (jmx == INT32_MAX || vmx < v[u]) { vmx = v[u]; jmx = j + u * G; }
+      }
+    }
+    for (; j < o1; j += G) {
+      const C v = E::load(lt + j);
+      if (jmn == INT32_MAX || v < vmn) { vmn = v; jmn = j; }
+      if (jmx == INT32_MAX || vmx < v) { vmx = v; jmx = j; }
+    }
+  }
+  if constexpr (G > 1) group_lex<G>(vmn, jmn, vmx, jmx);
+  if (valid && sub == 0) write_result<T>(p, c, bb, s < c0, e > c1, vmn, g_base + jmn, vmx, g_base + jmx);
+  const int64_t elast = readlane(e, 63);
+  b += kWave / G;
+  return !(elast >= c1 || b >= p.nb);
+}
+
+// Lanes per bin for a staged chunk of `len` elements with bins of about
+// `avg` elements, from a cost model in instructions: rounds x (strided
+// element steps + the group reduction + fixed per-round work).  64 means one
+// bin at a time across the whole wavefront.
+__device__ inline int staged_group(double len, double avg) {
+  const double bins = len / avg + 1.0;
+  double best = 0.0;
+  int g = 1;
+  const int gs[3] = {1, 4, 16};
+  for (int k = 0; k < 3; k++) {
+    const double G = gs[k];
+    const double rounds = ceil(bins * G / 64.0);
+    const double cost = rounds * (avg / G * 4.0 + 16.0 * (k == 0 ? 0 : (k == 1 ? 2 : 4)) + 40.0);
+    if (k == 0 || cost < best) { best = cost; g = gs[k]; }
+  }
+  const double wave = bins * (avg / 64.0 * 4.0 + 200.0);
+  return wave < best ? 64 : g;
+}
 
 template <typename T>
 __device__ void scan_chunk_staged(const ScanParams &p, int64_t c, int lane, u32x4 *lds) {
@@ -729,12 +838,28 @@ __device__ void scan_chunk_staged(const ScanParams &p, int64_t c, int lane, u32x
   const T *lt = (const T *)lds;
   const int64_t g_base = vc0 * VEC - p.shift;  // global index of lt[0]
 
-  int64_t b = first_bin(p.edges, p.n, p.nb, c0, lane);
+  const CeilMulDiv cm = closed_bins(p.n, p.nb);
+  int64_t b = uniform(first_bin(p.edges, cm, p.n, p.nb, c0, lane));
+  const int G = staged_group((double)(c1 - c0), (double)p.n / (double)p.nb);
+  if (G == 1) {
+    while (staged_round<T, 1>(p, cm, c, c0, c1, lt, g_base, b, lane)) {}
+    return;
+  }
+  if (G == 4) {
+    while (staged_round<T, 4>(p, cm, c, c0, c1, lt, g_base, b, lane)) {}
+    return;
+  }
+  if (G == 16) {
+    while (staged_round<T, 16>(p, cm, c, c0, c1, lt, g_base, b, lane)) {}
+    return;
+  }
+  // long bins: one segment at a time across the wavefront (short pieces at
+  // the chunk's ends one per lane)
   for (;;) {
     const int64_t bb = b + lane;
     const bool inb = bb < p.nb;
-    const int64_t s = edge_at(p.edges, p.n, p.nb, bb);
-    const int64_t e = edge_at(p.edges, p.n, p.nb, bb + 1);
+    const int64_t s = edge_at(p.edges, cm, p.n, p.nb, bb);
+    const int64_t e = edge_at(p.edges, cm, p.n, p.nb, bb + 1);
     const int64_t lo = s > c0 ? s : c0;
     const int64_t hi = e < c1 ? e : c1;
     const bool valid = inb && lo < hi;
@@ -757,14 +882,30 @@ __device__ void scan_chunk_staged(const ScanParams &p, int64_t c, int lane, u32x
       const int k = __builtin_ctzll(big);
       big &= big - 1;
       const int64_t slo = readlane(lo, k), shi = readlane(hi, k);
-      // per lane: elements slo + lane + 64 i in index order, strict compares
+      // per lane: elements slo + lane + 64 i in index order, strict compares,
+      // four LDS reads in flight per step
       C vmn = E::highest(), vmx = E::lowest();
-      int64_t imn = INT64_MAX, imx = INT64_MAX;
-      for (int64_t i = slo + lane; i < shi; i += kWave) {
-        const C v = E::load(lt + (i - g_base));
-        if (imn == INT64_MAX || v < vmn) { vmn = v; imn = i; }
-        if (imx == INT64_MAX || vmx < v) { vmx = v; imx = i; }
+      int32_t jmn = INT32_MAX, jmx = INT32_MAX;  // offsets from slo
+      const T *q = lt + (slo - g_base);
+      const int32_t len = (int32_t)(shi - slo);
+      for (int32_t j0 = lane; j0 < len; j0 += 4 * kWave) {
+        C v[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+          const int32_t j = j0 + u * kWave;
+          v[u] = E::load(q + (j < len ? j : 0));
+        }
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+          const int32_t j = j0 + u * kWave;
+          if (j < len) {
+            if (jmn == INT32_MAX || v[u] < vmn) { vmn = v[u]; jmn = j; }
+            if (jmx == INT32_MAX || vmx < v[u]) { vmx = v[u]; jmx = j; }
+          }
+        }
       }
+      const int64_t imn = jmn == INT32_MAX ? INT64_MAX : slo + jmn;
+      const int64_t imx = jmx == INT32_MAX ? INT64_MAX : slo + jmx;
       const C wmn = wave_min(vmn), wmx = wave_max(vmx);
       const int64_t rmn = wave_min(imn != INT64_MAX && vmn == wmn ? imn : INT64_MAX);
       const int64_t rmx = wave_min(imx != INT64_MAX && vmx == wmx ? imx : INT64_MAX);
@@ -822,10 +963,33 @@ __device__ void merged_bin(const MergeParams &p, int64_t s, int64_t e, int64_t b
   imx = wave_min(kmx == wkmx ? jmx : INT64_MAX);
 }
 
+// The same merge by one lane alone, the bin's partials in chunk order (the
+// lexicographic minimum does not depend on the order): for bins that span a
+// few chunks, where a wavefront per bin would leave most lanes idle.
+__device__ inline void merged_bin_lane(const MergeParams &p, int64_t s, int64_t e, int64_t bin, int64_t &imn,
+                                       int64_t &imx) {
+  const int64_t cs = (s + p.shift) / p.chunk, ce = (e - 1 + p.shift) / p.chunk;
+  if (cs == ce) {
+    imn = p.binres[2 * bin];
+    imx = p.binres[2 * bin + 1];
+    return;
+  }
+  uint64_t kmn = ~0ull, kmx = 0;
+  int64_t jmn = INT64_MAX, jmx = INT64_MAX;
+  for (int64_t c = cs; c <= ce; c++) {
+    const Partial q = (c == cs) ? p.partR[c] : p.partL[c];
+    lex_min(kmn, jmn, q.kmin, q.imin);
+    lex_max(kmx, jmx, q.kmax, q.imax);
+  }
+  imn = jmn;
+  imx = jmx;
+}
+
 // Bin b clipped to [0, n) (caller edges are not trusted to stay in range).
 __device__ inline void bin_range(const MergeParams &p, int64_t bin, int64_t &s, int64_t &e) {
-  s = edge_at(p.edges, p.n, p.nb, bin);
-  e = edge_at(p.edges, p.n, p.nb, bin + 1);
+  const CeilMulDiv cm = closed_bins(p.n, p.nb);
+  s = edge_at(p.edges, cm, p.n, p.nb, bin);
+  e = edge_at(p.edges, cm, p.n, p.nb, bin + 1);
   s = s < 0 ? 0 : (s > p.n ? p.n : s);
   e = e < s ? s : (e > p.n ? p.n : e);
 }

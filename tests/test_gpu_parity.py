@@ -178,6 +178,41 @@ def test_x_classified_chunks(ts, oracle_mod, xclass):
         ts.set_tuning()
 
 
+@pytest.mark.parametrize("dtype", ALL)
+def test_staged_lanes_per_bin(ts, oracle_mod, dtype):
+    """LDS-staged chunks reduce a bin with 1, 4, 16 or 64 lanes depending on
+    the bin length; every width must give the first occurrence, also when
+    the extreme repeats across the lanes of one group (tie runs)."""
+    n = 120011
+    y = S.walk(n, dtype, seed=41)
+    S.tie_runs(y, 0.3, seed=42)
+    ts.set_tuning(-1, -1, -1, 1, -1)
+    try:
+        for avg in (3, 30, 150, 700, 3000):
+            for algo, per in (("minmax", 2), ("m4", 4)):
+                n_out = per * max(1, n // avg)
+                say(f"[staged] {np.dtype(dtype).name} avg={avg} {algo} n_out={n_out}")
+                assert np.array_equal(gpu(ts, algo, y, n_out), orc(oracle_mod, algo, y, n_out)), (avg, algo)
+    finally:
+        ts.set_tuning()
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.uint8, np.int64, np.float16])
+def test_many_bins_compaction(ts, oracle_mod, dtype):
+    """Above 65,536 bins the compaction runs over many workgroups (block sums,
+    their scan, then the writes); n <= n_out fills 0..n-1 from many
+    workgroups."""
+    n = 1_000_003
+    y = S.walk(n, dtype, seed=51)
+    x = S.timestamps(n, 40, seed=52)
+    for xx in (None, x):
+        for algo, n_out in (("minmax", 300_000), ("m4", 400_000), ("minmax", 131_074), ("m4", 1_600_000)):
+            say(f"[many bins] {np.dtype(dtype).name} x={xx is not None} {algo} {n_out}")
+            assert np.array_equal(gpu(ts, algo, y, n_out, xx), orc(oracle_mod, algo, y, n_out, xx))
+        say(f"[many bins] {np.dtype(dtype).name} x={xx is not None} minmaxlttb 40000")
+        assert np.array_equal(gpu(ts, "minmaxlttb", y, 40_000, xx, 4), orc(oracle_mod, "minmaxlttb", y, 40_000, xx, 4))
+
+
 @pytest.mark.parametrize("dtype", [np.int8, np.float16, np.float32, np.float64, np.int64])
 def test_misaligned_series_pointer(ts, oracle_mod, dtype):
     """Slices start at any element: the scan realigns to 16-byte vectors."""
