@@ -229,12 +229,28 @@ BatchArgs args(const ts_plan *p, const void *d_table, int64_t *out, int64_t *cou
 }  // namespace
 
 int tsds::batch_enqueue(const ts_plan *p, const void *d_table, int64_t *out, int64_t *counts, void *ws,
-                        hipStream_t st) {
+                        hipStream_t st, bool fan) {
   const BatchArgs a = args(p, d_table, out, counts, ws);
   hipError_t e;
   if (p->any_x && (e = launch_batch_edges(a, st)) != hipSuccess) return api_fail(TS_ERR_HIP, "batch edges launch failed");
-  for (int g = 0; g < 22; g++) {
-    if (p->group_total[g] == 0) continue;
+  // groups by bytes, largest first (the largest stays on st)
+  std::vector<int> order;
+  for (int g = 0; g < 22; g++)
+    if (p->group_total[g] > 0) order.push_back(g);
+  std::stable_sort(order.begin(), order.end(), [p](int u, int v) {
+    return p->group_total[u] * (int64_t)esize(u % 11) > p->group_total[v] * (int64_t)esize(v % 11);
+  });
+  const bool use_side = fan && p->side[0] && order.size() > 1;
+  int used = 0;
+  if (use_side) {
+    if ((e = hipEventRecord(p->ev_fork, st)) != hipSuccess) return api_fail(TS_ERR_HIP, "fork event failed");
+    used = std::min<int>((int)order.size() - 1, ts_plan::kSide);
+    for (int k = 0; k < used; k++)
+      if ((e = hipStreamWaitEvent(p->side[k], p->ev_fork, 0)) != hipSuccess)
+        return api_fail(TS_ERR_HIP, "fork wait failed");
+  }
+  for (size_t k = 0; k < order.size(); k++) {
+    const int g = order[k];
     BatchGroup bg;
     bg.cb = (const int64_t *)((const char *)d_table + p->group_off_cb[g]);
     bg.tix = (const int32_t *)((const char *)d_table + p->group_off_tix[g]);
@@ -242,8 +258,13 @@ int tsds::batch_enqueue(const ts_plan *p, const void *d_table, int64_t *out, int
     bg.total = p->group_total[g];
     bg.ydt = g % 11;
     bg.stage = g / 11;
-    if ((e = launch_batch_scan(a, bg, p->grid_blocks, st)) != hipSuccess)
+    const hipStream_t s = (use_side && k > 0) ? p->side[(k - 1) % used] : st;
+    if ((e = launch_batch_scan(a, bg, p->grid_blocks, s)) != hipSuccess)
       return api_fail(TS_ERR_HIP, "batch scan launch failed");
+  }
+  for (int k = 0; k < used; k++) {
+    if ((e = hipEventRecord(p->ev_join[k], p->side[k])) != hipSuccess) return api_fail(TS_ERR_HIP, "join event failed");
+    if ((e = hipStreamWaitEvent(st, p->ev_join[k], 0)) != hipSuccess) return api_fail(TS_ERR_HIP, "join wait failed");
   }
   if ((e = launch_batch_merge(a, st)) != hipSuccess) return api_fail(TS_ERR_HIP, "batch merge launch failed");
   if ((e = launch_batch_compact(a, st)) != hipSuccess) return api_fail(TS_ERR_HIP, "batch compact launch failed");
@@ -253,8 +274,36 @@ int tsds::batch_enqueue(const ts_plan *p, const void *d_table, int64_t *out, int
 
 namespace {
 
-int enqueue(const ts_plan *p, int64_t *out, int64_t *counts, void *ws, hipStream_t st) {
-  return batch_enqueue(p, p->d_table, out, counts, ws, st);
+// Side streams and fork/join events of a plan, on the plan's device.
+int ensure_side(ts_plan *p) {
+  if (p->side[0]) return TS_OK;
+  int cur = 0;
+  if (hipGetDevice(&cur) != hipSuccess) return api_fail(TS_ERR_HIP, "no HIP device");
+  if (cur != p->device && hipSetDevice(p->device) != hipSuccess) return api_fail(TS_ERR_HIP, "cannot select the plan's device");
+  bool ok = hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming) == hipSuccess;
+  for (int k = 0; ok && k < ts_plan::kSide; k++)
+    ok = hipStreamCreateWithFlags(&p->side[k], hipStreamNonBlocking) == hipSuccess &&
+         hipEventCreateWithFlags(&p->ev_join[k], hipEventDisableTiming) == hipSuccess;
+  if (cur != p->device) (void)hipSetDevice(cur);
+  if (!ok) return api_fail(TS_ERR_HIP, "side stream creation failed");
+  return TS_OK;
+}
+
+void free_side(ts_plan *p) {
+  for (int k = 0; k < ts_plan::kSide; k++) {
+    if (p->side[k]) (void)hipStreamDestroy(p->side[k]);
+    if (p->ev_join[k]) (void)hipEventDestroy(p->ev_join[k]);
+    p->side[k] = nullptr;
+    p->ev_join[k] = nullptr;
+  }
+  if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
+  p->ev_fork = nullptr;
+}
+
+int enqueue(ts_plan *p, int64_t *out, int64_t *counts, void *ws, hipStream_t st) {
+  int rc = ensure_side(p);
+  if (rc) return rc;
+  return batch_enqueue(p, p->d_table, out, counts, ws, st, true);
 }
 
 void drop_graph(ts_plan *p) {
@@ -383,6 +432,7 @@ int ts_batch_run(ts_plan *p, int64_t *out_idx, int64_t *counts, void *ws, size_t
     hipError_t e;
     if (!p->cap_stream && (e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking)) != hipSuccess)
       return api_fail(TS_ERR_HIP, "capture stream creation failed");
+    if ((rc = ensure_side(p))) return rc;  // streams and events exist before the capture starts
     if ((e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
       return api_fail(TS_ERR_HIP, "graph capture failed to start");
     rc = enqueue(p, out_idx, counts, ws, p->cap_stream);
@@ -481,6 +531,7 @@ int ts_batch_autotune(ts_plan *p, int64_t *out_idx, int64_t *counts, void *ws, s
 void ts_plan_free(ts_plan *p) {
   if (!p) return;
   drop_graph(p);
+  free_side(p);
   if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
   if (p->d_table) (void)hipFree(p->d_table);
   delete p;

@@ -34,6 +34,12 @@ struct ts_plan {
   void *d_table = nullptr;
   size_t table_bytes = 0;
   int device = 0;
+  // side streams (default priority) on which the scans of different element
+  // types overlap, joined back before the merge; created on first use
+  static constexpr int kSide = 3;
+  hipStream_t side[kSide] = {nullptr, nullptr, nullptr};
+  hipEvent_t ev_fork = nullptr;
+  hipEvent_t ev_join[kSide] = {nullptr, nullptr, nullptr};
   // graph
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
@@ -51,7 +57,11 @@ size_t batch_table_bytes(ts_plan *p);
 // Writes the device table image (batch_table_bytes bytes) to dst.
 void batch_pack_table(const ts_plan *p, char *dst);
 // Enqueues the batch kernels using a device table already holding the image.
-int batch_enqueue(const ts_plan *p, const void *d_table, int64_t *out, int64_t *counts, void *ws, hipStream_t st);
+// With fan set and the plan's side streams created, the scans of different
+// element types run on up to 1 + kSide streams (forked from and joined back
+// to st, so the caller sees one ordered sequence on st).
+int batch_enqueue(const ts_plan *p, const void *d_table, int64_t *out, int64_t *counts, void *ws, hipStream_t st,
+                  bool fan = false);
 // Validation of one task (same rules as the single-series calls).
 int batch_check_task(const ts_task &t);
 
