@@ -178,15 +178,21 @@ int ts_batch_plan(const ts_task *tasks, int64_t n_tasks, ts_plan **plan);
 size_t ts_batch_workspace_bytes(const ts_plan *plan);
 int64_t ts_batch_out_size(const ts_plan *plan);
 
-/* Runs every task: one persistent argmin/argmax launch over the whole work
- * list (mixed dtypes and algorithms), one merge launch over all bins, one
- * compaction launch (one workgroup per task) and, if there are MinMaxLTTB
- * tasks, one LTTB launch (one workgroup per task).  Outputs are identical to
- * one single-series call per task.  use_graph != 0: the launches are captured
- * once into a hipGraph (re-captured when out_idx, counts or ws change) and
- * replayed with one hipGraphLaunch on `stream`.  out_idx: device int64
- * [ts_batch_out_size]; counts: device int64[n_tasks]; ws: device,
- * 256-byte aligned, >= ts_batch_workspace_bytes. */
+/* Runs every task: one persistent argmin/argmax launch per element type
+ * present (and per chunk kind: plain or LDS-staged), one merge launch over
+ * all bins (a wavefront per bin for long bins, a thread per bin for short
+ * ones), one compaction launch (one workgroup per task) and, if there are
+ * MinMaxLTTB tasks, one LTTB launch (one workgroup per task).  The scans of
+ * different element types run concurrently on up to three side streams
+ * (default priority) owned by the plan, forked from `stream` by an event and
+ * joined back to it before the merge, so the caller sees one ordered
+ * sequence on `stream`.  Outputs are identical to one single-series call per
+ * task.  use_graph != 0: the launches are captured once into a hipGraph
+ * (re-captured when out_idx, counts or ws change) and replayed with one
+ * hipGraphLaunch on `stream`.  out_idx: device int64 [ts_batch_out_size];
+ * counts: device int64[n_tasks]; ws: device, 256-byte aligned, >=
+ * ts_batch_workspace_bytes.  Calls on one plan must not overlap (the side
+ * streams and the graph belong to the plan). */
 int ts_batch_run(ts_plan *plan, int64_t *out_idx, int64_t *counts, void *ws, size_t ws_bytes, void *stream,
                  int use_graph);
 

@@ -382,7 +382,7 @@ int ts_batch_plan(const ts_task *tasks, int64_t n_tasks, ts_plan **out_plan) {
     delete p;
     return api_fail(TS_ERR_HIP, "no HIP device");
   }
-  p->grid_blocks = (int64_t)cus * 6;
+  p->grid_blocks = (int64_t)cus * 16;
   p->ws_bytes = batch_layout(p, kMinChunk);        // largest chunk count of the tuning space
   batch_layout(p, p->chunk_bytes);
   int rc = upload(p);
@@ -484,9 +484,9 @@ int ts_batch_autotune(ts_plan *p, int64_t *out_idx, int64_t *counts, void *ws, s
   int cus = 256;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess)
     return api_fail(TS_ERR_HIP, "device query failed");
-  const int64_t chunks[] = {8192, 16384, 32768, 65536};
+  const int64_t chunks[] = {16384, 32768, 65536};
   const int32_t smalls[] = {32, 128, 512};
-  const int64_t grids[] = {(int64_t)cus * 4, (int64_t)cus * 6, (int64_t)cus * 8};
+  const int64_t grids[] = {(int64_t)cus * 4, (int64_t)cus * 8, (int64_t)cus * 16};
   hipEvent_t a, b;
   if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
     return api_fail(TS_ERR_HIP, "event creation failed");

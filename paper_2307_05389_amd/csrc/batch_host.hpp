@@ -27,7 +27,7 @@ struct ts_plan {
   bool any_x = false;
   int64_t max_m = 0;        // largest MinMaxLTTB candidate capacity
   // tuning
-  int64_t chunk_bytes = 16384;
+  int64_t chunk_bytes = 65536;
   int32_t small = 128;
   int64_t grid_blocks = 0;
   // device table
