@@ -11,7 +11,11 @@ timed region.
 Printed: one JSON line with the input throughput (GB/s of y, the bytes the
 algorithm must read), the roofline of the dominant kernel (the scan; its
 duration measured with HIP events recorded by the library on the call's
-stream), and the CPU oracle timed on the host as a baseline.
+stream), and the CPU oracle timed on the host as a baseline.  Unless
+--no-extra: the other configurations (MinMax 1e6, MinMaxLTTB 5e8, plain
+LTTB 1e8), batched vs plain (512 series) and served vs plain (zoom requests
+over 64 resident series).  The oracle runs only in the CPU-baseline leg
+(the baseline timing and the parity samples); --no-cpu-baseline skips it.
 
     python bench.py [--steps K] [--warmup W] [--workload m4x|minmax|minmaxlttb]
 """
@@ -99,11 +103,12 @@ def cpu_baseline(name, x, y, w, budget_s=12.0):
                       f"{med * 1e3:.1f} ms"}, res
 
 
-def bench_batched(seed=3, n_series=512, reps=10):
+def bench_batched(seed=3, n_series=512, reps=10, check_oracle=True):
     """Batched vs plain on the mixed batch: 512 series, lengths log-uniform in
-    1e4..2e7, dtypes f32/f16/i16/u8, MinMax / M4, n_out 500..4000."""
+    1e4..2e7, dtypes f32/f16/i16/u8, MinMax / M4, n_out 500..4000.  With
+    check_oracle (part of the CPU-baseline leg), a sample of tasks is also
+    recomputed by the oracle on the host."""
     import torch
-    import oracle
     import paper_2307_05389_amd as tsds
     import synthetic as S
     specs = S.batch_specs(n_series, seed=seed)
@@ -160,14 +165,17 @@ def bench_batched(seed=3, n_series=512, reps=10):
     cnt_h = cnts.cpu().tolist()
     identical = all(torch.equal(batched[i], outs[i][: cnt_h[i]]) for i in range(len(specs)))
     # oracle on a sample of tasks
-    rng = np.random.default_rng(0)
-    sample = sorted(rng.choice(len(specs), 6, replace=False).tolist())
-    ok = True
-    for i in sample:
-        s = specs[i]
-        yh = ys[i].cpu().numpy()
-        exp = getattr(oracle, s["algo"])(yh, s["n_out"])
-        ok &= bool(np.array_equal(batched[i].cpu().numpy(), exp))
+    ok = None
+    if check_oracle:
+        import oracle
+        rng = np.random.default_rng(0)
+        sample = sorted(rng.choice(len(specs), 6, replace=False).tolist())
+        ok = True
+        for i in sample:
+            s = specs[i]
+            yh = ys[i].cpu().numpy()
+            exp = getattr(oracle, s["algo"])(yh, s["n_out"])
+            ok &= bool(np.array_equal(batched[i].cpu().numpy(), exp))
     b.close()
     return {
         "workload": "512 series, lengths log-uniform 1e4..2e7 (sum %d points, %.2f GB), dtypes f32/f16/i16/u8, "
@@ -182,7 +190,7 @@ def bench_batched(seed=3, n_series=512, reps=10):
     }
 
 
-def bench_served(full=False, n_series=64, n_points=200_000_000):
+def bench_served(full=False, n_series=64, n_points=200_000_000, check_oracle=True):
     """Serving: 64 resident series of 2e8 float32 points with int64 timestamps
     (gaps 1..100); Poisson arrivals of zoom/pan requests (window width
     log-uniform 0.1%..100% of the range, n_out 800..4000, MinMaxLTTB ratio 4);
@@ -264,19 +272,84 @@ def bench_served(full=False, n_series=64, n_points=200_000_000):
     plain.close()
     by_k, reqs = served_first
     out["identical_served_vs_plain"] = all(np.array_equal(by_k[k]["indices"], pk[k]["indices"]) for k in by_k)
-    # oracle on a few requests (window copied to the host)
-    import oracle
-    ok = True
-    for k in (n_warm, n_warm + 1, n_warm + 2):
-        r, q = by_k[k], reqs[k]
-        x, y = series[q["series"]]
-        xh = x[r["i0"]: r["i1"]].cpu().numpy()
-        yh = y[r["i0"]: r["i1"]].cpu().numpy()
-        exp = r["i0"] + oracle.minmaxlttb(yh, q["n_out"], 4, x=xh)
-        ok &= bool(np.array_equal(exp, r["indices"]))
+    # oracle on a few requests (window copied to the host; CPU-baseline leg)
+    ok = None
+    if check_oracle:
+        import oracle
+        ok = True
+        for k in (n_warm, n_warm + 1, n_warm + 2):
+            r, q = by_k[k], reqs[k]
+            x, y = series[q["series"]]
+            xh = x[r["i0"]: r["i1"]].cpu().numpy()
+            yh = y[r["i0"]: r["i1"]].cpu().numpy()
+            exp = r["i0"] + oracle.minmaxlttb(yh, q["n_out"], 4, x=xh)
+            ok &= bool(np.array_equal(exp, r["indices"]))
     out["oracle_sample_bit_exact"] = ok
     del series
     torch.cuda.empty_cache()
+    return out
+
+
+def bench_configs(reps_small=200, reps_big=10, check_oracle=True):
+    """The other configurations: MinMax at 1e6 (latency-bound), MinMaxLTTB at
+    5e8 (preselection scan + candidate LTTB) and plain LTTB at 1e8 (the
+    paper's Table 1 LTTB row, one workgroup walking the buckets), each timed
+    with HIP events around the whole call and, with check_oracle (part of
+    the CPU-baseline leg), checked against the oracle on the host."""
+    import torch
+    import paper_2307_05389_amd as tsds
+    import synthetic as S
+    dev = torch.device("cuda:0")
+    st = torch.cuda.current_stream(dev)
+    out = []
+
+    def timed(fn, reps):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(st)
+            fn()
+            b.record(st)
+            b.synchronize()
+            ts.append(a.elapsed_time(b))
+        return float(np.median(ts))
+
+    cases = [
+        ("minmax", "MinMax no x, float32 random walk, N=1e6, n_out=1000", lambda: S.walk(1_000_000, np.float32, seed=0),
+         1000, reps_small, "tsdownsample MinMax float32 N=1e6 parallel: 0.23 ms (17.4 GB/s)"),
+        ("minmaxlttb", "MinMaxLTTB no x, float32 random walk with 5% constant runs, N=5e8, n_out=2000, ratio 4",
+         lambda: S.tie_runs(S.walk(500_000_000, np.float32, seed=2), 0.05, seed=2), 2000, reps_big,
+         "tsdownsample MinMaxLTTB float32 N=1e9 parallel: 89.17 ms (44.9 GB/s); N=1e8: 9.56 ms"),
+        ("lttb", "plain LTTB no x, float32 random walk, N=1e8, n_out=2000", lambda: S.walk(100_000_000, np.float32, seed=5),
+         2000, reps_big, "tsdownsample LTTB float32 N=1e8 (sequential only): 173.72 ms (2.3 GB/s)"),
+    ]
+    for algo, desc, gen, n_out, reps, paper in cases:
+        log(f"[bench] config {algo}: generating")
+        y = gen()
+        yd = torch.from_numpy(y).to(dev)
+        o = torch.empty(n_out, dtype=torch.int64, device=dev)
+        c = torch.zeros(1, dtype=torch.int64, device=dev)
+        need = tsds.workspace_bytes(algo, yd, n_out, minmax_ratio=4)
+        ws = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)
+        fn = lambda: tsds.downsample_into(algo, yd, n_out, o, c, minmax_ratio=4, workspace=ws, stream=st)
+        ms = timed(fn, reps)
+        got = o[: int(c.item())].cpu().numpy()
+        parity = None
+        if check_oracle:
+            import oracle
+            ref = oracle.minmaxlttb(y, n_out, 4) if algo == "minmaxlttb" else getattr(oracle, algo)(y, n_out)
+            parity = "bit-exact" if np.array_equal(got, ref) else "MISMATCH"
+        out.append({"algo": algo, "workload": desc, "n": int(y.size), "n_out": n_out, "ms": round(ms, 4),
+                    "GBps": round(y.nbytes / ms / 1e6, 1), "points_per_s": round(y.size / ms * 1e3, 1),
+                    "frac_of_hbm_peak": round(y.nbytes / ms / 1e6 / HBM_PEAK_GBS, 4),
+                    "parity_vs_oracle": parity,
+                    "paper_context": paper + "; 32-thread Xeon E5-2650 v2, other hardware"})
+        log(f"[bench] config {algo}: {ms:.3f} ms")
+        del yd, ws, y
+        torch.cuda.empty_cache()
     return out
 
 
@@ -287,7 +360,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="m4x", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extra", action="store_true", help="skip the batched and served comparisons")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the other configurations and the batched and served comparisons")
     ap.add_argument("--serve-full", action="store_true", help="served sweep at 100..20000 QPS, 10000 requests each")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain device copy of y (for counter calibration)")
@@ -384,9 +458,11 @@ def main():
     if not args.no_extra:
         del yd, xd, ws
         torch.cuda.empty_cache()
-        res["batched"] = bench_batched()
+        chk = not args.no_cpu_baseline
+        res["other_configs"] = bench_configs(check_oracle=chk)
+        res["batched"] = bench_batched(check_oracle=chk)
         torch.cuda.empty_cache()
-        res["served"] = bench_served(full=args.serve_full)
+        res["served"] = bench_served(full=args.serve_full, check_oracle=chk)
     print(json.dumps(res), flush=True)
 
 

@@ -178,22 +178,55 @@ static ScanPlan scan_plan(int ydt, int xdt, int64_t n, int64_t nb, size_t base) 
   return p;
 }
 
+// LTTB walk variants: buckets of a few points (transition map over all
+// anchors), long buckets of a plain series (hull candidates), else one
+// workgroup walking every point.
+enum LttbMode { kLttbSeq = 0, kLttbSmall = 1, kLttbHull = 2 };
+
+static LttbMode lttb_mode(bool has_sel, int64_t m_max, int64_t n_out) {
+  const int64_t nb = n_out - 2;
+  const int64_t maxb = (m_max - 2 + nb - 1) / nb, minb = (m_max - 2) / nb;
+  if (maxb <= 32 && m_max <= (int64_t)1 << 30) return kLttbSmall;
+  if (!has_sel && minb >= kHullMinBucket && maxb < ((int64_t)1 << 30)) return kLttbHull;
+  return kLttbSeq;
+}
+
 struct LttbPlan {
-  size_t off_cx = 0, off_cy = 0, off_next = 0, off_entry = 0, bytes = 0;
+  LttbMode mode = kLttbSeq;
+  size_t off_cx = 0, off_cy = 0, off_next = 0, off_entry = 0, off_ccnt = 0, off_cidx = 0, off_ccx = 0,
+         off_ccy = 0, off_hnext = 0, off_hjump = 0, off_hflag = 0, bytes = 0;
 };
 
-static LttbPlan lttb_plan(int64_t m_max, int64_t n_out, size_t base) {
+static LttbPlan lttb_plan(int64_t m_max, int64_t n_out, bool has_sel, size_t base) {
   LttbPlan p;
+  p.mode = lttb_mode(has_sel, m_max, n_out);
   size_t o = base;
   const size_t nb = (size_t)(n_out - 2);
   p.off_cx = o;
   o = align256(o + sizeof(double) * nb);
   p.off_cy = o;
   o = align256(o + sizeof(double) * nb);
-  p.off_next = o;
-  o = align256(o + sizeof(int32_t) * 2 * (size_t)m_max);
-  p.off_entry = o;
-  o = align256(o + sizeof(int32_t) * (lttb_group_count(n_out) + 1));
+  if (p.mode == kLttbSmall) {
+    p.off_next = o;
+    o = align256(o + sizeof(int32_t) * 2 * (size_t)m_max);
+    p.off_entry = o;
+    o = align256(o + sizeof(int32_t) * (lttb_group_count(n_out) + 1));
+  } else if (p.mode == kLttbHull) {
+    p.off_ccnt = o;
+    o = align256(o + sizeof(int32_t) * nb);
+    p.off_cidx = o;
+    o = align256(o + sizeof(int64_t) * nb * kHullCand);
+    p.off_ccx = o;
+    o = align256(o + sizeof(double) * nb * kHullCand);
+    p.off_ccy = o;
+    o = align256(o + sizeof(double) * nb * kHullCand);
+    p.off_hnext = o;
+    o = align256(o + nb * kHullCand);
+    p.off_hjump = o;
+    o = align256(o + (size_t)lttb_hull_group((int64_t)nb) * kHullCand);
+    p.off_hflag = o;
+    o = align256(o + sizeof(int32_t));
+  }
   p.bytes = o;
   return p;
 }
@@ -367,15 +400,14 @@ static MmlPlan mml_plan(const ts_series &s, int64_t n_out, int64_t ratio) {
   } else {
     p.m_max = s.n;
   }
-  p.lt = lttb_plan(p.m_max, n_out, o);
+  p.lt = lttb_plan(p.m_max, n_out, !p.presel_all, o);
   p.bytes = p.lt.bytes;
   return p;
 }
 
 static int run_lttb(const ts_series &s, const int64_t *sel, int64_t m, const int64_t *m_dev, int64_t m_max,
-                    int64_t n_out, const LttbPlan &lp, void *ws, int64_t *out, int64_t *out_count, bool small,
-                    hipStream_t st) {
-  LttbParams p;
+                    int64_t n_out, const LttbPlan &lp, void *ws, int64_t *out, int64_t *out_count, hipStream_t st) {
+  LttbParams p{};
   p.x = s.x;
   p.x_dtype = s.x_dtype;
   p.y = s.y;
@@ -387,25 +419,33 @@ static int run_lttb(const ts_series &s, const int64_t *sel, int64_t m, const int
   p.n_out = n_out;
   p.cx = (double *)wsp(ws, lp.off_cx);
   p.cy = (double *)wsp(ws, lp.off_cy);
-  p.next = (int32_t *)wsp(ws, lp.off_next);
-  p.entry = (int32_t *)wsp(ws, lp.off_entry);
+  if (lp.mode == kLttbSmall) {
+    p.next = (int32_t *)wsp(ws, lp.off_next);
+    p.entry = (int32_t *)wsp(ws, lp.off_entry);
+  }
+  if (lp.mode == kLttbHull) {
+    p.cand_cnt = (int32_t *)wsp(ws, lp.off_ccnt);
+    p.cand_idx = (int64_t *)wsp(ws, lp.off_cidx);
+    p.cand_x = (double *)wsp(ws, lp.off_ccx);
+    p.cand_y = (double *)wsp(ws, lp.off_ccy);
+    p.hnext = (uint8_t *)wsp(ws, lp.off_hnext);
+    p.hjump = (uint8_t *)wsp(ws, lp.off_hjump);
+    p.hflag = (int32_t *)wsp(ws, lp.off_hflag);
+  }
   p.out = out;
   p.out_count = out_count;
   hipError_t e;
   if ((e = launch_lttb_centres(p, st)) != hipSuccess) return hip_fail(e, "lttb centres");
-  if (small) {
-    if ((e = launch_lttb_small(p, st)) != hipSuccess) return hip_fail(e, "lttb walk");
-  } else {
-    if ((e = launch_lttb_seq(p, st)) != hipSuccess) return hip_fail(e, "lttb walk");
+  switch (lp.mode) {
+    case kLttbSmall: e = launch_lttb_small(p, st); break;
+    case kLttbHull:
+      if ((e = launch_lttb_hull(p, st)) != hipSuccess) return hip_fail(e, "lttb hulls");
+      e = launch_lttb_hull_walk(p, st);
+      break;
+    default: e = launch_lttb_seq(p, st); break;
   }
+  if (e != hipSuccess) return hip_fail(e, "lttb walk");
   return TS_OK;
-}
-
-// Largest LTTB bucket for which the transition-map walk is used.
-static bool lttb_small_buckets(int64_t m, int64_t n_out) {
-  const int64_t nb = n_out - 2;
-  const int64_t maxb = (m - 2 + nb - 1) / nb;
-  return maxb <= 32 && m <= (int64_t)1 << 30;
 }
 
 int api_fail(int code, const char *msg) { return fail(code, "%s", msg); }
@@ -428,7 +468,7 @@ size_t ts_workspace_bytes(int algo, const ts_series *s, int64_t n_out, int64_t m
   switch (algo) {
     case TS_MINMAX: return scan_plan(s->y_dtype, s->x_dtype, s->n, n_out / 2, 0).bytes;
     case TS_M4: return scan_plan(s->y_dtype, s->x_dtype, s->n, n_out / 4, 0).bytes;
-    case TS_LTTB: return lttb_plan(s->n, n_out, 0).bytes;
+    case TS_LTTB: return lttb_plan(s->n, n_out, false, 0).bytes;
     case TS_MINMAXLTTB: return mml_plan(*s, n_out, minmax_ratio).bytes;
   }
   return 0;
@@ -467,10 +507,9 @@ int ts_lttb(const ts_series *s, int64_t n_out, int64_t *out_idx, int64_t *out_co
   if (s->n <= n_out) return write_all(s->n, out_idx, out_count, st);
   if ((unsigned __int128)s->n * (unsigned __int128)n_out >= ((unsigned __int128)1 << 62))
     return fail(TS_ERR_ARG, "n * n_out too large");
-  const LttbPlan lp = lttb_plan(s->n, n_out, 0);
+  const LttbPlan lp = lttb_plan(s->n, n_out, false, 0);
   if ((rc = check_ws(ws, ws_bytes, lp.bytes))) return rc;
-  return run_lttb(*s, nullptr, s->n, nullptr, s->n, n_out, lp, ws, out_idx, out_count,
-                  lttb_small_buckets(s->n, n_out), st);
+  return run_lttb(*s, nullptr, s->n, nullptr, s->n, n_out, lp, ws, out_idx, out_count, st);
 }
 
 int ts_minmaxlttb(const ts_series *s, int64_t n_out, int64_t minmax_ratio, int64_t *out_idx, int64_t *out_count,
@@ -486,8 +525,7 @@ int ts_minmaxlttb(const ts_series *s, int64_t n_out, int64_t minmax_ratio, int64
   if ((unsigned __int128)pl.m_max * (unsigned __int128)n_out >= ((unsigned __int128)1 << 62))
     return fail(TS_ERR_ARG, "n * n_out too large");
   if (pl.presel_all) {
-    return run_lttb(*s, nullptr, s->n, nullptr, s->n, n_out, pl.lt, ws, out_idx, out_count,
-                    lttb_small_buckets(s->n, n_out), st);
+    return run_lttb(*s, nullptr, s->n, nullptr, s->n, n_out, pl.lt, ws, out_idx, out_count, st);
   }
   // Preselection over the interior points 1..n-2.
   ts_series in = *s;
@@ -499,8 +537,7 @@ int ts_minmaxlttb(const ts_series *s, int64_t n_out, int64_t minmax_ratio, int64
   int64_t *cand = (int64_t *)wsp(ws, pl.off_cand);
   int64_t *m_dev = (int64_t *)wsp(ws, pl.off_m);
   if ((rc = run_scan(in, npre / 2, 0, pl.scan, ws, cand + 1, m_dev, 1, s->n, st))) return rc;
-  return run_lttb(*s, cand, -1, m_dev, pl.m_max, n_out, pl.lt, ws, out_idx, out_count,
-                  lttb_small_buckets(pl.m_max, n_out), st);
+  return run_lttb(*s, cand, -1, m_dev, pl.m_max, n_out, pl.lt, ws, out_idx, out_count, st);
 }
 
 int ts_bin_edges(const ts_series *s, int64_t nb, int64_t *edges, void *stream) {

@@ -100,9 +100,27 @@ struct LttbParams {
   int32_t *entry;         // [groups + 1] workspace
   int64_t *out;
   int64_t *out_count;
+  // hull-pruned walk of plain LTTB (long buckets); NULL when unused
+  int32_t *cand_cnt;      // [nb] candidates of bucket k, 0: walk every point of it
+  int64_t *cand_idx;      // [nb * kHullCand]
+  double *cand_x;         // [nb * kHullCand]
+  double *cand_y;         // [nb * kHullCand]
+  uint8_t *hnext;         // [nb * kHullCand] pick in bucket k for each candidate anchor of bucket k-1
+  uint8_t *hjump;         // [groups * kHullCand] exit of each group for each entry anchor
+  int32_t *hflag;         // [1] 1 when the map walk has written the result
 };
 
+// Hull-pruned plain LTTB: used for buckets of at least kHullMinBucket points;
+// at most kHullCand candidates are kept per bucket (else the bucket is walked
+// in full) and kHullLane hull points per lane segment.
+constexpr int64_t kHullMinBucket = 512;
+constexpr int kHullCand = 64;
+constexpr int kHullLane = 24;
+
 hipError_t launch_lttb_centres(const LttbParams &p, hipStream_t st);
+hipError_t launch_lttb_hull(const LttbParams &p, hipStream_t st);
+hipError_t launch_lttb_hull_walk(const LttbParams &p, hipStream_t st);
+int64_t lttb_hull_group(int64_t nb);
 hipError_t launch_lttb_small(const LttbParams &p, hipStream_t st);
 hipError_t launch_lttb_seq(const LttbParams &p, hipStream_t st);
 

@@ -20,6 +20,16 @@ __device__ inline bool int_coord_y(const LttbParams &p) {
   return p.y_dtype != TS_F16 && p.y_dtype != TS_F32 && p.y_dtype != TS_F64;
 }
 
+// Bytes of one element of a ts dtype.
+__device__ inline int elem_bytes(int dt) {
+  switch (dt) {
+    case TS_I8: case TS_U8: return 1;
+    case TS_I16: case TS_U16: case TS_F16: return 2;
+    case TS_I32: case TS_U32: case TS_F32: return 4;
+  }
+  return 8;
+}
+
 // Exact value of an integer element as a 128-bit integer.
 __device__ inline __int128 int_val(const void *a, int dt, int64_t s) {
   switch (dt) {

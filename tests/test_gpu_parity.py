@@ -290,6 +290,46 @@ def test_lttb_parity(ts, oracle_mod, dtype, with_x):
         assert near == 0 and np.array_equal(got, exp)
 
 
+def hull_cases(n, dtype, seed):
+    """Series for the hull-pruned LTTB walk: a random walk, the same with long
+    constant runs (exact area ties), a constant series (every area zero) and
+    a parabola (every point on the hull, so slices overflow and buckets are
+    walked in full)."""
+    walk = S.walk(n, dtype, seed=seed)
+    ties = S.tie_runs(S.walk(n, dtype, seed=seed + 1), 0.5, seed=seed + 2, lmin=600, lmax=5000)
+    j = np.arange(n, dtype=np.float64)
+    if np.issubdtype(dtype, np.floating):
+        par = ((j - n / 2) ** 2 / (4 * n)).astype(dtype)  # below 25,001: finite in float16
+    else:
+        par = (((j % 2000) - 1000) ** 2 // 64).astype(dtype)
+    mixed = walk.copy()
+    mixed[n // 2:] = par[n // 2:]  # some buckets pruned, some walked in full
+    return {"walk": walk, "ties": ties, "const": np.full(n, 3, dtype), "parabola": par, "mixed": mixed}
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64, np.int16, np.uint8, np.float16, np.int64])
+def test_lttb_hull_walk(ts, oracle_mod, dtype):
+    """Plain LTTB with buckets of at least 512 points walks only each bucket's
+    convex-hull vertices and first point.  Step by step against the oracle:
+    the same pick except near ties of the stated tolerance."""
+    n = 400_003
+    xs = {"none": None,
+          "i64dup": np.repeat(S.timestamps((n + 2) // 3, 50, seed=64), 3)[:n],
+          "f64": S.timestamps(n, 20, seed=65).astype(np.float64) * 0.25}
+    for name, y in hull_cases(n, dtype, seed=66).items():
+        for xname, x in xs.items():
+            for n_out in (500, 100, 3):
+                say(f"[lttb hull] {np.dtype(dtype).name} {name} x={xname} n_out={n_out}")
+                got = gpu(ts, "lttb", y, n_out, x)
+                near = stepwise_check(oracle_mod, y, n_out, got, x=x)
+                if near:
+                    say(f"    near-tie acceptances: {near}")
+    y = S.walk(100_000, dtype, seed=67)
+    say(f"[lttb hull] {np.dtype(dtype).name} MinMaxLTTB keeping every point")
+    got = gpu(ts, "minmaxlttb", y, 150, None, 1000)
+    stepwise_check(oracle_mod, y, 150, got)
+
+
 @pytest.mark.parametrize("dtype", [np.float32, np.float64, np.int16, np.uint8, np.float16])
 @pytest.mark.parametrize("xname", ["none", "i64", "f64"])
 def test_minmaxlttb_parity(ts, oracle_mod, dtype, xname):
