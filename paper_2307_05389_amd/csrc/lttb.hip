@@ -318,6 +318,9 @@ __device__ inline double cross3(double ox, double oy, double ax, double ay, doub
   return (ax - ox) * (by - oy) - (ay - oy) * (bx - ox);
 }
 
+// Turn pops per point in the branch-free slice chains.
+constexpr int kHullPops = 3;
+
 // Monotone chain over points added in index order (offsets from the bucket
 // start `lo`), its stack (offset, Y and, with x, X) in LDS; without x, X is
 // the index lo + offset.  upper: the upper hull (keeps clockwise turns), else
@@ -329,20 +332,85 @@ struct HullChain {
   int64_t lo;
   int n, cap, stride;  // entry i at [i * stride] (lane stacks interleave, stride 64)
   bool upper, over;
+  // the top two entries are also kept in registers: a push reads no LDS and a
+  // pop reads only the entry that becomes second
+  double tx, ty, ux, uy;
   __device__ HullChain(int32_t *o, double *x, double *y, int64_t lo_, int capacity, int str, bool up)
-      : so(o), sx(x), sy(y), lo(lo_), n(0), cap(capacity), stride(str), upper(up), over(false) {}
-  __device__ double X(int i) const { return HX ? sx[i * stride] : (double)(lo + so[i * stride]); }
+      : so(o), sx(x), sy(y), lo(lo_), n(0), cap(capacity), stride(str), upper(up), over(false), tx(0), ty(0),
+        ux(0), uy(0) {}
+  // without x the X coordinate is the offset from the bucket start (cross
+  // products of small integers, identical to those of the absolute index)
+  __device__ double X(int i) const { return HX ? sx[i * stride] : (double)so[i * stride]; }
   __device__ double Y(int i) const { return sy[i * stride]; }
+  __device__ void pop() {
+    n--;
+    tx = ux;
+    ty = uy;
+    if (n >= 2) {
+      ux = X(n - 2);
+      uy = Y(n - 2);
+    }
+  }
+  // Branch-free variant for whole wavefronts of independent chains: at most
+  // one pop for a repeated X and kHullPops turn pops per point (further pops
+  // are skipped, so the stack may keep extra points but never loses a hull
+  // vertex: every pop is justified by two points of the set).  The entries
+  // that may become second are read from LDS up front, in one round trip.
+  __device__ void add_bounded(int32_t j, double xj, double yj) {
+    constexpr int K = HX ? kHullPops + 1 : kHullPops;  // without x no X repeats
+    // ex/ey[i]: the entry that becomes second after i + 1 pops; popping
+    // shifts this window (selects only, no indexed registers)
+    double ex[K], ey[K];
+#pragma unroll
+    for (int i = 0; i < K; i++) {
+      const int e = n - 3 - i >= 0 ? n - 3 - i : 0;
+      ex[i] = X(e);
+      ey[i] = Y(e);
+    }
+    const bool same = HX && n > 0 && xj == tx;
+    const bool act = !over && !(same && (upper ? !(yj > ty) : !(yj < ty)));
+    auto cond_pop = [&](bool pp) {
+      if (pp) {
+        n--;
+        tx = ux;
+        ty = uy;
+        ux = ex[0];
+        uy = ey[0];
+#pragma unroll
+        for (int i = 0; i + 1 < K; i++) {
+          ex[i] = ex[i + 1];
+          ey[i] = ey[i + 1];
+        }
+      }
+    };
+    cond_pop(act && same);
+#pragma unroll
+    for (int s = 0; s < kHullPops; s++) {
+      const double c = cross3(ux, uy, tx, ty, xj, yj);
+      cond_pop(act && n >= 2 && (upper ? c >= 0.0 : c <= 0.0));
+    }
+    if (act && n == cap) over = true;
+    if (act && !over) {
+      so[n * stride] = j;
+      if (HX) sx[n * stride] = xj;
+      sy[n * stride] = yj;
+      n++;
+      ux = tx;
+      uy = ty;
+      tx = xj;
+      ty = yj;
+    }
+  }
   __device__ void add(int32_t j, double xj, double yj) {
     if (over) return;
-    if (n > 0 && xj == X(n - 1)) {  // same X as the top: keep the first highest (lowest)
-      if (upper ? !(yj > Y(n - 1)) : !(yj < Y(n - 1))) return;
-      n--;
+    if (n > 0 && xj == tx) {  // same X as the top: keep the first highest (lowest)
+      if (upper ? !(yj > ty) : !(yj < ty)) return;
+      pop();
     }
     while (n >= 2) {
-      const double c = cross3(X(n - 2), Y(n - 2), X(n - 1), Y(n - 1), xj, yj);
+      const double c = cross3(ux, uy, tx, ty, xj, yj);
       if (upper ? c >= 0.0 : c <= 0.0)
-        n--;
+        pop();
       else
         break;
     }
@@ -354,60 +422,90 @@ struct HullChain {
     if (HX) sx[n * stride] = xj;
     sy[n * stride] = yj;
     n++;
+    ux = tx;
+    uy = ty;
+    tx = xj;
+    ty = yj;
   }
 };
 
 // Points loaded per lane before they are added (independent loads in flight).
 constexpr int kHullBatch = 16;
 
-// Raw bits of elements j0 .. j0 + kHullBatch - 1 (clamped to jmax) of a
-// series of dtype dt, the element width chosen once for the whole batch so
-// that the loads are issued back to back.
-__device__ inline void load_raw_batch(const void *a, int dt, int64_t j0, int64_t jmax, uint64_t (&raw)[kHullBatch]) {
-  const int64_t last = jmax;
-  switch (elem_bytes(dt)) {
-    case 1:
+// Elements j0 .. j0 + kHullBatch - 1 (clamped to jmax) of a series of dtype
+// dt as the doubles the walk uses (dbl_val): the dtype switch is taken once
+// per batch and the loads inside it are issued back to back.
+template <typename V>
+__device__ inline void batch_as_double(const V *a, int64_t j0, int64_t jmax, double (&out)[kHullBatch]) {
+  V v[kHullBatch];
 #pragma unroll
-      for (int u = 0; u < kHullBatch; u++) raw[u] = ((const uint8_t *)a)[j0 + u < last ? j0 + u : last];
-      break;
-    case 2:
+  for (int u = 0; u < kHullBatch; u++) v[u] = a[j0 + u < jmax ? j0 + u : jmax];
 #pragma unroll
-      for (int u = 0; u < kHullBatch; u++) raw[u] = ((const uint16_t *)a)[j0 + u < last ? j0 + u : last];
-      break;
-    case 4:
+  for (int u = 0; u < kHullBatch; u++) out[u] = (double)v[u];
+}
+
+__device__ inline void load_batch(const void *a, int dt, int64_t j0, int64_t jmax, double (&out)[kHullBatch]) {
+  switch (dt) {
+    case TS_I8: batch_as_double((const int8_t *)a, j0, jmax, out); break;
+    case TS_I16: batch_as_double((const int16_t *)a, j0, jmax, out); break;
+    case TS_I32: batch_as_double((const int32_t *)a, j0, jmax, out); break;
+    case TS_I64: batch_as_double((const int64_t *)a, j0, jmax, out); break;
+    case TS_U8: batch_as_double((const uint8_t *)a, j0, jmax, out); break;
+    case TS_U16: batch_as_double((const uint16_t *)a, j0, jmax, out); break;
+    case TS_U32: batch_as_double((const uint32_t *)a, j0, jmax, out); break;
+    case TS_U64: batch_as_double((const uint64_t *)a, j0, jmax, out); break;
+    case TS_F16: {
+      uint16_t v[kHullBatch];
+      const uint16_t *h = (const uint16_t *)a;
 #pragma unroll
-      for (int u = 0; u < kHullBatch; u++) raw[u] = ((const uint32_t *)a)[j0 + u < last ? j0 + u : last];
-      break;
-    default:
+      for (int u = 0; u < kHullBatch; u++) v[u] = h[j0 + u < jmax ? j0 + u : jmax];
 #pragma unroll
-      for (int u = 0; u < kHullBatch; u++) raw[u] = ((const uint64_t *)a)[j0 + u < last ? j0 + u : last];
+      for (int u = 0; u < kHullBatch; u++) out[u] = (double)(float)__builtin_bit_cast(_Float16, v[u]);
       break;
+    }
+    case TS_F32: batch_as_double((const float *)a, j0, jmax, out); break;
+    default: batch_as_double((const double *)a, j0, jmax, out); break;
   }
 }
 
-// The raw bits of one element as the double the walk uses (dbl_val).
-__device__ inline double raw_to_double(uint64_t r, int dt) {
-  switch (dt) {
-    case TS_I8: return (double)(int8_t)(uint8_t)r;
-    case TS_I16: return (double)(int16_t)(uint16_t)r;
-    case TS_I32: return (double)(int32_t)(uint32_t)r;
-    case TS_I64: return (double)(int64_t)r;
-    case TS_U8: return (double)(uint8_t)r;
-    case TS_U16: return (double)(uint16_t)r;
-    case TS_U32: return (double)(uint32_t)r;
-    case TS_U64: return (double)r;
-    case TS_F16: return (double)(float)__builtin_bit_cast(_Float16, (uint16_t)r);
-    case TS_F32: return (double)__builtin_bit_cast(float, (uint32_t)r);
-    case TS_F64: return __builtin_bit_cast(double, r);
+// Coordinates of a batch of points lo + j0 + u of the series.
+template <bool HX>
+__device__ inline void load_points(const LttbParams &p, int64_t lo, int64_t j0, int64_t jmax,
+                                   double (&xs)[kHullBatch], double (&ys)[kHullBatch]) {
+  load_batch(p.y, p.y_dtype, j0, jmax, ys);
+  if (HX) {
+    load_batch(p.x, p.x_dtype, j0, jmax, xs);
+  } else {
+    const double xb = (double)(j0 - lo);  // offset from the bucket start
+#pragma unroll
+    for (int u = 0; u < kHullBatch; u++) xs[u] = xb + (double)u;
   }
-  return 0.0;
 }
+
+template <bool HX, bool HC>
+__device__ void feed_raw(const LttbParams &p, int64_t lo, int64_t a, int64_t b, HullChain<HC> &h) {
+  for (int64_t j0 = a; j0 < b; j0 += kHullBatch) {
+    double xs[kHullBatch], ys[kHullBatch];
+    load_points<HX>(p, lo, lo + j0, lo + b - 1, xs, ys);
+#pragma unroll
+    for (int u = 0; u < kHullBatch; u++)
+      if (j0 + u < b) h.add((int32_t)(j0 + u), xs[u], ys[u]);
+  }
+}
+
+// Group chains of the two-level merge: 8 groups of 8 slices per chain kind.
+constexpr int kHullGroup = 32;
 
 template <bool HX>
 __global__ __launch_bounds__(64) void k_lttb_hull(LttbParams p) {
+  // lane stacks, interleaved: entry i of lane l of chain c at [c][i * 64 + l]
   __shared__ int32_t so[2][64 * kHullLane];
   __shared__ double sx[HX ? 2 : 1][HX ? 64 * kHullLane : 1], sy[2][64 * kHullLane];
   __shared__ int32_t nsl[2][64];
+  // group chains: entry i of group g of chain c at [i * 16 + c * 8 + g]
+  __shared__ int32_t go[16 * kHullGroup];
+  __shared__ double gx[HX ? 16 * kHullGroup : 1], gy[16 * kHullGroup];
+  __shared__ int32_t ngr[16];
   __shared__ int32_t mo[2][kHullCand];
   __shared__ double mx[2][kHullCand], my[2][kHullCand];
   __shared__ int32_t mg_n[2];
@@ -419,46 +517,72 @@ __global__ __launch_bounds__(64) void k_lttb_hull(LttbParams p) {
   // 1. one slice per lane (slices in index order), points loaded in batches
   {
     const int64_t s0 = len * lane / 64, s1 = len * (lane + 1) / 64;
-    // lane stacks interleaved (entry i of lane l at i * 64 + l): conflict-free LDS banks
     HullChain<HX> up(so[0] + lane, HX ? sx[0] + lane : nullptr, sy[0] + lane, lo, kHullLane, 64, true);
     HullChain<HX> dn(so[1] + lane, HX ? sx[HX ? 1 : 0] + lane : nullptr, sy[1] + lane, lo, kHullLane, 64, false);
     for (int64_t j0 = s0; j0 < s1; j0 += kHullBatch) {
-      uint64_t ry[kHullBatch], rx[kHullBatch];
-      load_raw_batch(p.y, p.y_dtype, lo + j0, lo + s1 - 1, ry);
-      if (HX) load_raw_batch(p.x, p.x_dtype, lo + j0, lo + s1 - 1, rx);
-      for (int u = 0; u < kHullBatch && j0 + u < s1; u++) {
-        const double xj = HX ? raw_to_double(rx[u], p.x_dtype) : (double)(lo + j0 + u);
-        const double yj = raw_to_double(ry[u], p.y_dtype);
-        up.add((int32_t)(j0 + u), xj, yj);
-        dn.add((int32_t)(j0 + u), xj, yj);
+      double xs[kHullBatch], ys[kHullBatch];
+      load_points<HX>(p, lo, lo + j0, lo + s1 - 1, xs, ys);
+#pragma unroll
+      for (int u = 0; u < kHullBatch; u++) {
+        if (j0 + u < s1) {
+          up.add_bounded((int32_t)(j0 + u), xs[u], ys[u]);
+          dn.add_bounded((int32_t)(j0 + u), xs[u], ys[u]);
+        }
       }
     }
-    nsl[0][lane] = up.over ? -1 : up.n;
+    nsl[0][lane] = up.over ? -1 : up.n;  // -1: the slice's points are re-read
     nsl[1][lane] = dn.over ? -1 : dn.n;
   }
   __syncthreads();
-  // 2. lane 0 merges the upper chains, lane 1 the lower ones (a slice's hull
-  //    keeps every point of the bucket's hull that lies in the slice)
-  if (lane < 2) {
-    const int c = lane;
-    HullChain<true> h(mo[c], mx[c], my[c], lo, kHullCand, 1, c == 0);
-    bool bad = false;
-    for (int sl = 0; sl < 64 && !bad; sl++) {
+  // 2. lanes 0-15 merge 8 slices each (lanes 0-7 upper, 8-15 lower); a
+  //    slice's hull keeps every point of the bucket's hull in the slice
+  if (lane < 16) {
+    const int c = lane >> 3, g = lane & 7;
+    HullChain<HX> h(go + lane, HX ? gx + lane : nullptr, gy + lane, lo, kHullGroup, 16, c == 0);
+    for (int sl = 8 * g; sl < 8 * g + 8; sl++) {
       const int32_t cn = nsl[c][sl];
       if (cn < 0) {
-        bad = true;
-        break;
+        feed_raw<HX>(p, lo, len * sl / 64, len * (sl + 1) / 64, h);
+        continue;
       }
       for (int e = 0; e < cn; e++) {
         const int q = e * 64 + sl;
-        const double xq = HX ? sx[HX ? c : 0][q] : (double)(lo + so[c][q]);
-        h.add(so[c][q], xq, sy[c][q]);
+        h.add(so[c][q], HX ? sx[HX ? c : 0][q] : (double)so[c][q], sy[c][q]);
       }
     }
-    mg_n[c] = (bad || h.over) ? -1 : h.n;
+    ngr[lane] = h.over ? -1 : h.n;
   }
   __syncthreads();
-  // 3. candidates: the bucket's first point and both chains, in index order
+  // 3. lane 0 merges the upper group chains, lane 1 the lower ones
+  if (lane < 2) {
+    const int c = lane;
+    HullChain<true> h(mo[c], mx[c], my[c], lo, kHullCand, 1, c == 0);
+    for (int g = 0; g < 8; g++) {
+      const int gi = c * 8 + g;
+      const int32_t cn = ngr[gi];
+      if (cn >= 0) {
+        for (int e = 0; e < cn; e++) {
+          const int q = e * 16 + gi;
+          h.add(go[q], HX ? gx[q] : (double)go[q], gy[q]);
+        }
+        continue;
+      }
+      for (int sl = 8 * g; sl < 8 * g + 8; sl++) {  // the group's chain overflowed
+        const int32_t sn = nsl[c][sl];
+        if (sn < 0) {
+          feed_raw<HX>(p, lo, len * sl / 64, len * (sl + 1) / 64, h);
+          continue;
+        }
+        for (int e = 0; e < sn; e++) {
+          const int q = e * 64 + sl;
+          h.add(so[c][q], HX ? sx[HX ? c : 0][q] : (double)so[c][q], sy[c][q]);
+        }
+      }
+    }
+    mg_n[c] = h.over ? -1 : h.n;
+  }
+  __syncthreads();
+  // 4. candidates: the bucket's first point and both chains, in index order
   if (lane == 0) {
     const int32_t nu = mg_n[0], nd = mg_n[1];
     int32_t total = 0;
@@ -474,7 +598,7 @@ __global__ __launch_bounds__(64) void k_lttb_hull(LttbParams p) {
           return;
         }
         p.cand_idx[base + total] = lo + j;
-        p.cand_x[base + total] = xj;
+        p.cand_x[base + total] = HX ? xj : (double)(lo + j);  // absolute coordinates for the walk
         p.cand_y[base + total] = yj;
         total++;
       };

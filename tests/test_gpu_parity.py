@@ -304,7 +304,11 @@ def hull_cases(n, dtype, seed):
         par = (((j % 2000) - 1000) ** 2 // 64).astype(dtype)
     mixed = walk.copy()
     mixed[n // 2:] = par[n // 2:]  # some buckets pruned, some walked in full
-    return {"walk": walk, "ties": ties, "const": np.full(n, 3, dtype), "parabola": par, "mixed": mixed}
+    # convex bumps of 64 points on a walk: slice hulls overflow and are re-read
+    bumps = (S.walk(n, np.float64, seed=seed + 3) * 50 + ((j % 64) - 32) ** 2).astype(dtype) \
+        if np.issubdtype(dtype, np.floating) or np.dtype(dtype).itemsize >= 4 else walk
+    return {"walk": walk, "ties": ties, "const": np.full(n, 3, dtype), "parabola": par, "mixed": mixed,
+            "bumps": bumps}
 
 
 @pytest.mark.parametrize("dtype", [np.float32, np.float64, np.int16, np.uint8, np.float16, np.int64])
