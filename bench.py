@@ -365,7 +365,10 @@ def main():
     ap.add_argument("--serve-full", action="store_true", help="served sweep at 100..20000 QPS, 10000 requests each")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain device copy of y (for counter calibration)")
+    ap.add_argument("--legs", default="configs,batched,served",
+                    help="comma list of the extra legs to run after the headline: configs, batched, served")
     args = ap.parse_args()
+    legs = set(x for x in args.legs.split(",") if x)
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the path shards by series or by index range, see the design notes)", file=sys.stderr)
@@ -459,10 +462,13 @@ def main():
         del yd, xd, ws
         torch.cuda.empty_cache()
         chk = not args.no_cpu_baseline
-        res["other_configs"] = bench_configs(check_oracle=chk)
-        res["batched"] = bench_batched(check_oracle=chk)
-        torch.cuda.empty_cache()
-        res["served"] = bench_served(full=args.serve_full, check_oracle=chk)
+        if "configs" in legs:
+            res["other_configs"] = bench_configs(check_oracle=chk)
+        if "batched" in legs:
+            res["batched"] = bench_batched(check_oracle=chk)
+            torch.cuda.empty_cache()
+        if "served" in legs:
+            res["served"] = bench_served(full=args.serve_full, check_oracle=chk)
     print(json.dumps(res), flush=True)
 
 

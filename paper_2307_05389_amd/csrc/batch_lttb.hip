@@ -2,18 +2,16 @@
 // workgroup per task computes the bucket centres and walks the buckets with
 // the transition map (see lttb.hip).  Built with IEEE mode and no FMA
 // contraction, like the single-series LTTB kernels.
+#include <algorithm>
+
 #include "common.hpp"
 #include "internal.hpp"
 #include "lttb_core.hpp"
 
 namespace tsds {
 
-__global__ __launch_bounds__(1024) void k_batch_lttb(BatchArgs a) {
-  extern __shared__ int32_t smem[];
-  const BatchTask &t = a.tasks[a.lttb_tasks[blockIdx.x]];
-  const int64_t task = a.lttb_tasks[blockIdx.x];
-  if (t.mode == 1) return;  // written by the compaction
-  LttbParams p;
+__device__ inline LttbParams task_lttb_params(const BatchArgs &a, const BatchTask &t, int64_t task) {
+  LttbParams p{};
   p.x = t.xf;
   p.x_dtype = t.xf ? t.xdt : TS_NONE;
   p.y = t.yf;
@@ -29,21 +27,51 @@ __global__ __launch_bounds__(1024) void k_batch_lttb(BatchArgs a) {
   p.entry = (int32_t *)(a.ws + t.o_entry);
   p.out = a.out + t.out_offset;
   p.out_count = a.counts + task;
+  return p;
+}
+
+// Transition maps of every MinMaxLTTB task: blockIdx.x = task, one thread per
+// anchor (strided over blockIdx.y); the centres are computed where they are
+// needed (the same sequential means the single-series kernel stores first).
+__global__ __launch_bounds__(256) void k_batch_lttb_map(BatchArgs a) {
+  const int64_t task = a.lttb_tasks[blockIdx.x];
+  const BatchTask &t = a.tasks[task];
+  if (t.mode == 1) return;
+  const LttbParams p = task_lttb_params(a, t, task);
+  const int64_t m = points_m(p);
+  if (m <= p.n_out) return;
+  for (int64_t an = (int64_t)blockIdx.y * blockDim.x + threadIdx.x; an < m - 1; an += (int64_t)gridDim.y * blockDim.x)
+    p.next[an] = lttb_map_one(p, m, an, true);
+}
+
+// The walk of each task along its map, one workgroup per task.
+__global__ __launch_bounds__(1024) void k_batch_lttb(BatchArgs a) {
+  extern __shared__ int32_t smem[];
+  const int64_t task = a.lttb_tasks[blockIdx.x];
+  const BatchTask &t = a.tasks[task];
+  if (t.mode == 1) return;  // written by the compaction
+  const LttbParams p = task_lttb_params(a, t, task);
   const int64_t m = points_m(p);
   if (m <= p.n_out) {
     copy_all(p, m);
     return;
   }
-  lttb_block_centres(p, m);
-  __syncthreads();
   const bool lds = a.lds_ok && t.m_max <= a.lds_m;
-  lttb_small_walk(p, m, lds ? smem : p.next, lds ? smem + a.lds_m : p.next + p.m_max,
-                  lttb_group_len(p.n_out - 2));
+  int32_t *next = p.next, *jump = p.next + p.m_max;
+  if (lds) {
+    for (int64_t i = threadIdx.x; i < m - 1; i += blockDim.x) smem[i] = p.next[i];
+    next = smem;
+    jump = smem + a.lds_m;
+    __syncthreads();
+  }
+  lttb_walk_map(p, m, next, jump, lttb_group_len(p.n_out - 2));
 }
 
 hipError_t launch_batch_lttb(const BatchArgs &a, hipStream_t st) {
   if (a.n_lttb == 0) return hipSuccess;
   const size_t lds = a.lds_ok ? (size_t)a.lds_m * 2 * sizeof(int32_t) : 0;
+  const int64_t ychunks = std::min<int64_t>((a.max_m + 255) / 256, 1024);
+  k_batch_lttb_map<<<dim3((unsigned)a.n_lttb, (unsigned)std::max<int64_t>(ychunks, 1)), dim3(256), 0, st>>>(a);
   k_batch_lttb<<<dim3((unsigned)a.n_lttb), dim3(1024), lds, st>>>(a);
   return hipGetLastError();
 }

@@ -163,6 +163,7 @@ struct BatchArgs {
   int32_t small;
   int32_t lds_ok;            // LTTB maps fit in LDS for every task
   int64_t lds_m;             // m capacity of the LDS maps
+  int64_t max_m;             // largest candidate capacity of a MinMaxLTTB task
 };
 
 hipError_t launch_batch_edges(const BatchArgs &a, hipStream_t st);

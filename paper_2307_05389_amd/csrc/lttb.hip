@@ -213,7 +213,18 @@ hipError_t launch_lttb_centres(const LttbParams &p, hipStream_t st) {
 
 // ---------------------------------------------------------------- small
 
-// next[] and jump[] live in LDS when `lds_ok`, else in global workspace.
+// The transition map of every anchor, one thread each over the whole GPU
+// (the map is the bulk of the small-bucket walk: a few dependent loads per
+// anchor through the candidate list), into p.next in global memory.
+__global__ __launch_bounds__(256) void k_lttb_map(LttbParams p) {
+  const int64_t m = points_m(p);
+  const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m <= p.n_out || a >= m - 1) return;
+  p.next[a] = lttb_map_one(p, m, a, false);
+}
+
+// The walk along the map by one workgroup; next[] (copied from global) and
+// jump[] live in LDS when `lds_ok`, else in global workspace.
 __global__ __launch_bounds__(1024) void k_lttb_small(LttbParams p, int32_t group, int lds_ok) {
   extern __shared__ int32_t smem[];
   const int64_t m = points_m(p);
@@ -221,13 +232,21 @@ __global__ __launch_bounds__(1024) void k_lttb_small(LttbParams p, int32_t group
     copy_all(p, m);
     return;
   }
-  lttb_small_walk(p, m, lds_ok ? smem : p.next, lds_ok ? smem + p.m_max : p.next + p.m_max, group);
+  int32_t *next = p.next, *jump = p.next + p.m_max;
+  if (lds_ok) {
+    for (int64_t a = threadIdx.x; a < m - 1; a += blockDim.x) smem[a] = p.next[a];
+    next = smem;
+    jump = smem + p.m_max;
+    __syncthreads();
+  }
+  lttb_walk_map(p, m, next, jump, group);
 }
 
 hipError_t launch_lttb_small(const LttbParams &p, hipStream_t st) {
   const int32_t group = lttb_group_len(p.n_out - 2);
   const size_t lds = (size_t)p.m_max * 2 * sizeof(int32_t);
   const int lds_ok = lds <= 128 * 1024;
+  k_lttb_map<<<dim3((unsigned)((p.m_max + 255) / 256)), dim3(256), 0, st>>>(p);
   k_lttb_small<<<dim3(1), dim3(1024), lds_ok ? lds : 0, st>>>(p, group, lds_ok);
   return hipGetLastError();
 }

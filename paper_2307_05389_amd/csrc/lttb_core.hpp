@@ -166,27 +166,39 @@ __device__ inline void lttb_block_centres(const LttbParams &p, int64_t m) {
   }
 }
 
+// Transition map entry of anchor a (a = 0 stands for the first point, before
+// bucket 0): the point of the next bucket the walk picks when the previous
+// pick is a.  The centre of that bucket comes from cx/cy when given, else it
+// is computed here (the same sequential mean).
+__device__ inline int32_t lttb_map_one(const LttbParams &p, int64_t m, int64_t a, bool own_centres) {
+  const int64_t nb = p.n_out - 2;
+  const int64_t k = a == 0 ? -1 : bucket_of(a, m, nb);
+  if (k == nb - 1) return (int32_t)(m - 1);
+  const int64_t lo = bucket_start(k + 1, m, nb), hi = bucket_start(k + 2, m, nb);
+  double Cx, Cy;
+  if (!own_centres) {
+    Cx = p.cx[k + 1];
+    Cy = p.cy[k + 1];
+  } else if (k + 1 == nb - 1) {
+    Cx = X_of(p, m - 1);
+    Cy = Y_of(p, m - 1);
+  } else {
+    const int64_t clo = bucket_start(k + 2, m, nb), chi = bucket_start(k + 3, m, nb);
+    Cx = coord_mean(p, 0, clo, chi);
+    Cy = coord_mean(p, 1, clo, chi);
+  }
+  return (int32_t)best_in_bucket(p, lo, hi, X_of(p, a), Y_of(p, a), Cx, Cy);
+}
+
 // LTTB walk over m > n_out points with buckets of a few points, by the whole
-// workgroup.  next[] and jump[] hold m_max int32 each (LDS or global).
-__device__ void lttb_small_walk(const LttbParams &p, int64_t m, int32_t *next, int32_t *jump, int32_t group) {
+// workgroup, from the transition map next[] (entries 0 .. m-2; see
+// lttb_map_one).  jump[] holds m int32 (LDS or global).
+__device__ void lttb_walk_map(const LttbParams &p, int64_t m, const int32_t *next, int32_t *jump, int32_t group) {
   const int64_t nb = p.n_out - 2;
   int32_t *entry = p.entry;
   const int64_t G = (nb + group - 1) / group;
 
-  // 1. transition map: next[a] = pick in bucket k+1 when the pick in bucket k
-  //    is a (a = 0 stands for the first point, before bucket 0).
-  for (int64_t a = threadIdx.x; a < m - 1; a += blockDim.x) {
-    const int64_t k = a == 0 ? -1 : bucket_of(a, m, nb);
-    if (k == nb - 1) {
-      next[a] = (int32_t)(m - 1);
-      continue;
-    }
-    const int64_t lo = bucket_start(k + 1, m, nb), hi = bucket_start(k + 2, m, nb);
-    next[a] = (int32_t)best_in_bucket(p, lo, hi, X_of(p, a), Y_of(p, a), p.cx[k + 1], p.cy[k + 1]);
-  }
-  __syncthreads();
-
-  // 2. group exits: for every possible entry a of group g (the first point
+  // 1. group exits: for every possible entry a of group g (the first point
   //    for g = 0, else any point of bucket g*group - 1), follow next[] over
   //    the group's buckets.  (group, entry) pairs are spread over threads.
   const int64_t P = (m - 2 + nb - 1) / nb + 1;  // >= largest bucket
@@ -203,7 +215,7 @@ __device__ void lttb_small_walk(const LttbParams &p, int64_t m, int32_t *next, i
   }
   __syncthreads();
 
-  // 3. chain over groups.
+  // 2. chain over groups.
   if (threadIdx.x == 0) {
     int32_t v = 0;
     for (int64_t g = 0; g < G; g++) {
@@ -213,7 +225,7 @@ __device__ void lttb_small_walk(const LttbParams &p, int64_t m, int32_t *next, i
   }
   __syncthreads();
 
-  // 4. group interiors in parallel.
+  // 3. group interiors in parallel.
   for (int64_t g = threadIdx.x; g < G; g += blockDim.x) {
     int32_t v = entry[g];
     const int64_t k1 = (g + 1) * group < nb ? (g + 1) * group : nb;
@@ -229,7 +241,14 @@ __device__ void lttb_small_walk(const LttbParams &p, int64_t m, int32_t *next, i
   }
 }
 
-// Transition-map group length for nb buckets (about sqrt(nb / 2)).
+// The whole small-bucket walk in one workgroup: the map (all anchors in
+// parallel), then lttb_walk_map.  next[] and jump[] hold m_max int32 each.
+__device__ void lttb_small_walk(const LttbParams &p, int64_t m, int32_t *next, int32_t *jump, int32_t group) {
+  for (int64_t a = threadIdx.x; a < m - 1; a += blockDim.x) next[a] = lttb_map_one(p, m, a, false);
+  __syncthreads();
+  lttb_walk_map(p, m, next, jump, group);
+}
+
 __host__ __device__ inline int32_t lttb_group_len(int64_t nb) {
   int32_t group = 1;
   while ((int64_t)group * group * 2 < nb) group *= 2;
