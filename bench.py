@@ -234,7 +234,7 @@ def bench_served(full=False, n_series=64, n_points=200_000_000, check_oracle=Tru
                     time.sleep(min(wait - 1e-4, 1e-3))
             elif len(done) < len(reqs):
                 time.sleep(2e-4)
-        lat, pts, bs = [], 0, []
+        lat, slat, pts, bs = [], [], 0, []
         first, last = None, 0.0
         by_k = {}
         for rid, r in done.items():
@@ -243,13 +243,17 @@ def bench_served(full=False, n_series=64, n_points=200_000_000, check_oracle=Tru
             if kk < n_warm:
                 continue
             lat.append(r["t_done"] - ta)
+            slat.append(r["t_done"] - r["t_submit"])
             pts += r["i1"] - r["i0"]
             bs.append(r["batch_size"])
             first = ta if first is None else min(first, ta)
             last = max(last, r["t_done"])
         lat = np.array(lat) * 1e3
+        slat = np.array(slat) * 1e3
         return {"qps": qps, "p50_ms": round(float(np.percentile(lat, 50)), 3),
                 "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                "server_p50_ms": round(float(np.percentile(slat, 50)), 3),
+                "server_p99_ms": round(float(np.percentile(slat, 99)), 3),
                 "points_per_s": round(pts / (last - first), 1),
                 "mean_batch": round(float(np.mean(bs)), 2)}, by_k, reqs
 

@@ -238,6 +238,8 @@ typedef struct {
   double t_submit;      /* ts_server_now() at submission */
   double t_done;        /* ts_server_now() when the indices were in host memory */
   int64_t batch_size;   /* requests in the batch it ran in */
+  double t_admit;       /* its batch was admitted to a slot (window search enqueued) */
+  double t_run;         /* the windows had arrived and the downsampling was enqueued */
 } ts_result;
 
 typedef struct ts_server ts_server;

@@ -60,7 +60,7 @@ struct Res {
   int32_t series;
   int32_t status;
   int64_t i0, i1;
-  double t_submit, t_done;
+  double t_submit, t_done, t_admit, t_run;
   int32_t batch;
   std::vector<int64_t> idx;
 };
@@ -78,6 +78,7 @@ struct Slot {
   ts_plan plan;
   std::vector<Req> batch;
   int state = FREE;
+  double t_admit = 0.0, t_run = 0.0;
 };
 
 }  // namespace
@@ -154,6 +155,7 @@ void free_slot(Slot &sl) {
 
 // FREE -> RESOLVING: window search for the slot's batch.
 int start_batch(ts_server *sv, Slot &sl) {
+  sl.t_admit = now_s();
   WindowBatch wb;
   memset(&wb, 0, sizeof wb);
   wb.count = (int32_t)sl.batch.size();
@@ -193,6 +195,7 @@ ts_series window_series(const ts_server *sv, const Slot &sl, int i) {
 
 // RESOLVING -> RUNNING: downsampling of every request on its window.
 int run_batch(ts_server *sv, Slot &sl) {
+  sl.t_run = now_s();
   const int nb = (int)sl.batch.size();
   const int64_t mo = sv->cfg.max_nout;
   if (sv->cfg.plain) {
@@ -244,6 +247,8 @@ void finish_batch(ts_server *sv, Slot &sl) {
     r.i1 = std::max(sl.h_ranges[2 * i + 1], r.i0);
     r.t_submit = sl.batch[i].t_submit;
     r.t_done = t;
+    r.t_admit = sl.t_admit;
+    r.t_run = sl.t_run;
     r.batch = nb;
     const int64_t c = sl.h_counts[i];
     const int64_t *src = sl.h_out + i * sv->cfg.max_nout;
@@ -271,6 +276,8 @@ void fail_batch(ts_server *sv, Slot &sl, int rc) {
     r.i0 = r.i1 = 0;
     r.t_submit = q.t_submit;
     r.t_done = now_s();
+    r.t_admit = sl.t_admit;
+    r.t_run = sl.t_run;
     r.batch = (int32_t)sl.batch.size();
     sv->done.push_back(std::move(r));
   }
@@ -379,7 +386,12 @@ int ts_server_create(const ts_series *series, int32_t n_series, const ts_server_
   }
   sv->grid_blocks = (int64_t)cus * 6;
   sv->slots.resize(sv->cfg.n_streams);
-  for (Slot &sl : sv->slots) sl.plan.grid_blocks = sv->grid_blocks;
+  // latency over throughput: short chunks (more wavefronts on small windows)
+  // and a grid that leaves room for the other slots' kernels
+  for (Slot &sl : sv->slots) {
+    sl.plan.grid_blocks = sv->grid_blocks;
+    sl.plan.chunk_bytes = 16384;
+  }
   for (Slot &sl : sv->slots) {
     int rc = alloc_slot(sv, sl);
     if (rc) {
@@ -435,6 +447,8 @@ int ts_server_poll(ts_server *sv, ts_result *res, int32_t max_results, int64_t *
     o.t_submit = r.t_submit;
     o.t_done = r.t_done;
     o.batch_size = r.batch;
+    o.t_admit = r.t_admit;
+    o.t_run = r.t_run;
     if (!r.idx.empty()) memcpy(idx + used, r.idx.data(), sizeof(int64_t) * r.idx.size());
     used += (int64_t)r.idx.size();
     sv->done.pop_front();

@@ -23,7 +23,7 @@ class TsResult(ctypes.Structure):
     _fields_ = [("id", ctypes.c_int64), ("series", ctypes.c_int32), ("status", ctypes.c_int32),
                 ("count", ctypes.c_int64), ("offset", ctypes.c_int64), ("i0", ctypes.c_int64),
                 ("i1", ctypes.c_int64), ("t_submit", ctypes.c_double), ("t_done", ctypes.c_double),
-                ("batch_size", ctypes.c_int64)]
+                ("batch_size", ctypes.c_int64), ("t_admit", ctypes.c_double), ("t_run", ctypes.c_double)]
 
 
 def _setup(lib):
@@ -84,6 +84,7 @@ class Server:
                 r = self._res[k]
                 out.append(dict(id=r.id, series=r.series, status=r.status, i0=r.i0, i1=r.i1,
                                 t_submit=r.t_submit, t_done=r.t_done, batch_size=r.batch_size,
+                                t_admit=r.t_admit, t_run=r.t_run,
                                 indices=self._idx[r.offset: r.offset + r.count].copy()))
             if n.value < 256:
                 return out
