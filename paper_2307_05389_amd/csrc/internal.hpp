@@ -198,8 +198,18 @@ struct WindowBatch {
   int32_t xdt[kMaxWindows];
   int32_t count;
   int64_t *ranges;
+  int64_t *host_ranges;  // host-mapped copy of ranges (NULL: none)
 };
 
 hipError_t launch_windows(const WindowBatch &wb, hipStream_t st);
+
+// Copies bytes with a kernel between device memory and host-mapped pinned
+// memory (the serving loop avoids memcpy calls, which can hold the calling
+// thread for milliseconds while other streams are busy).
+hipError_t launch_copy_bytes(void *dst, const void *src, size_t bytes, hipStream_t st);
+// Serving results to host-mapped memory: h_counts[i] = counts[i] and the
+// first counts[i] entries of row i (rows of `row` int64) into h_rows.
+hipError_t launch_export_rows(const int64_t *counts, const int64_t *rows, int64_t row, int n, int64_t *h_counts,
+                              int64_t *h_rows, hipStream_t st);
 
 }  // namespace tsds

@@ -75,6 +75,9 @@ struct Slot {
   size_t table_cap = 0, ws_cap = 0;
   int64_t *h_ranges = nullptr, *h_out = nullptr, *h_counts = nullptr;
   char *h_table = nullptr;
+  // device-side addresses of the host buffers
+  int64_t *m_ranges = nullptr, *m_out = nullptr, *m_counts = nullptr;
+  char *m_table = nullptr;
   ts_plan plan;
   std::vector<Req> batch;
   int state = FREE;
@@ -135,10 +138,18 @@ int alloc_slot(ts_server *sv, Slot &sl) {
   ok(hipMalloc(&sl.d_table, sl.table_cap));
   sl.ws_cap = std::max<size_t>(sv->cfg.arena_bytes, 256);
   ok(hipMalloc(&sl.ws, sl.ws_cap));
-  ok(hipHostMalloc((void **)&sl.h_ranges, sizeof(int64_t) * 2 * mb, hipHostMallocDefault));
-  ok(hipHostMalloc((void **)&sl.h_out, sizeof(int64_t) * mb * sv->cfg.max_nout, hipHostMallocDefault));
-  ok(hipHostMalloc((void **)&sl.h_counts, sizeof(int64_t) * mb, hipHostMallocDefault));
-  ok(hipHostMalloc((void **)&sl.h_table, sl.table_cap, hipHostMallocDefault));
+  // host buffers: pinned, mapped and coherent; kernels read and write them
+  // directly (see launch_copy_bytes)
+  ok(hipHostMalloc((void **)&sl.h_ranges, sizeof(int64_t) * 2 * mb, hipHostMallocCoherent));
+  ok(hipHostMalloc((void **)&sl.h_out, sizeof(int64_t) * mb * sv->cfg.max_nout, hipHostMallocCoherent));
+  ok(hipHostMalloc((void **)&sl.h_counts, sizeof(int64_t) * mb, hipHostMallocCoherent));
+  ok(hipHostMalloc((void **)&sl.h_table, sl.table_cap, hipHostMallocCoherent));
+  if (e == hipSuccess) {
+    ok(hipHostGetDevicePointer((void **)&sl.m_ranges, sl.h_ranges, 0));
+    ok(hipHostGetDevicePointer((void **)&sl.m_out, sl.h_out, 0));
+    ok(hipHostGetDevicePointer((void **)&sl.m_counts, sl.h_counts, 0));
+    ok(hipHostGetDevicePointer((void **)&sl.m_table, sl.h_table, 0));
+  }
   return e == hipSuccess ? TS_OK : api_fail(TS_ERR_HIP, "server slot allocation failed");
 }
 
@@ -160,6 +171,7 @@ int start_batch(ts_server *sv, Slot &sl) {
   memset(&wb, 0, sizeof wb);
   wb.count = (int32_t)sl.batch.size();
   wb.ranges = sl.d_ranges;
+  wb.host_ranges = sl.m_ranges;
   for (int i = 0; i < wb.count; i++) {
     const ts_series &s = sv->series[sl.batch[i].series];
     wb.x[i] = s.x;
@@ -169,9 +181,6 @@ int start_batch(ts_server *sv, Slot &sl) {
     wb.xdt[i] = s.x_dtype;
   }
   if (launch_windows(wb, sl.st) != hipSuccess) return TS_ERR_HIP;
-  if (hipMemcpyAsync(sl.h_ranges, sl.d_ranges, sizeof(int64_t) * 2 * wb.count, hipMemcpyDeviceToHost, sl.st) !=
-      hipSuccess)
-    return TS_ERR_HIP;
   if (hipEventRecord(sl.ev_ranges, sl.st) != hipSuccess) return TS_ERR_HIP;
   sl.state = RESOLVING;
   return TS_OK;
@@ -221,12 +230,11 @@ int run_batch(ts_server *sv, Slot &sl) {
     const size_t tb = batch_table_bytes(&sl.plan);
     if (need > sl.ws_cap || tb > sl.table_cap) return api_fail(TS_ERR_WORKSPACE, "batch exceeds the slot arena");
     batch_pack_table(&sl.plan, sl.h_table);
-    if (hipMemcpyAsync(sl.d_table, sl.h_table, tb, hipMemcpyHostToDevice, sl.st) != hipSuccess) return TS_ERR_HIP;
+    if (launch_copy_bytes(sl.d_table, sl.m_table, tb, sl.st) != hipSuccess) return TS_ERR_HIP;
     int rc = batch_enqueue(&sl.plan, sl.d_table, sl.d_out, sl.d_counts, sl.ws, sl.st);
     if (rc) return rc;
   }
-  if (hipMemcpyAsync(sl.h_counts, sl.d_counts, sizeof(int64_t) * nb, hipMemcpyDeviceToHost, sl.st) != hipSuccess ||
-      hipMemcpyAsync(sl.h_out, sl.d_out, sizeof(int64_t) * nb * mo, hipMemcpyDeviceToHost, sl.st) != hipSuccess ||
+  if (launch_export_rows(sl.d_counts, sl.d_out, mo, nb, sl.m_counts, sl.m_out, sl.st) != hipSuccess ||
       hipEventRecord(sl.ev_done, sl.st) != hipSuccess)
     return TS_ERR_HIP;
   sl.state = RUNNING;
