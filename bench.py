@@ -10,8 +10,8 @@ timed region.
 
 Printed: one JSON line with the input throughput (GB/s of y, the bytes the
 algorithm must read), the roofline of the dominant kernel (the scan; its
-duration measured with HIP events recorded by the library on the call's
-stream), and the CPU oracle timed on the host as a baseline.  Unless
+duration measured live with HIP events that the library's launch stamps with
+the dispatch's own start and end times), and the CPU oracle timed on the host as a baseline.  Unless
 --no-extra: the other configurations (MinMax 1e6, MinMaxLTTB 5e8, plain
 LTTB 1e8), batched vs plain (512 series) and served vs plain (zoom requests
 over 64 resident series).  The oracle runs only in the CPU-baseline leg

@@ -301,10 +301,11 @@ int ts_set_tuning(int64_t chunk_bytes, int32_t small_bin, int32_t scan_variant, 
 int ts_scan_config(int y_dtype, int x_dtype, int64_t n, int64_t nb, int32_t *variant, int64_t *chunk_bytes,
                    int32_t *kind);
 
-/* Timing hook: when both are non-NULL, the next compute calls record the
- * hipEvent_t `start` on their stream just before the argmin/argmax scan
- * kernel is launched and `stop` just after it, so a caller can time that
- * kernel alone.  Pass NULL, NULL to switch it off.  Process-wide. */
+/* Timing hook: when both are non-NULL, the next single-series compute calls
+ * launch the argmin/argmax scan kernel with hipExtLaunchKernel, which stamps
+ * the hipEvent_t `start` and `stop` (created by the caller) with that
+ * dispatch's own start and end times, so hipEventElapsedTime gives the
+ * kernel's duration alone.  Pass NULL, NULL to switch it off.  Process-wide. */
 int ts_profile_scan_events(void *start, void *stop);
 
 #ifdef __cplusplus

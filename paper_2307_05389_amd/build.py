@@ -16,7 +16,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libtsds.so")
 
-SOURCES = ["scan.hip", "window.hip", "lttb.hip", "api.cpp", "batch.hip", "batch_lttb.hip", "api_batch.cpp"]
+SOURCES = ["scan.hip", "select.hip", "window.hip", "lttb.hip", "api.cpp", "batch.hip", "batch_lttb.hip", "api_batch.cpp"]
 EXTRA_SOURCES = ["serve.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -40,6 +40,7 @@ def _sources():
 # The argmin/argmax scan compares values only and y holds no NaN by contract,
 # so its unit drops IEEE-mode NaN quieting in front of every min/max.
 PER_FILE = {"scan.hip": ["-fno-honor-nans", "-mno-amdgpu-ieee"],
+            "select.hip": ["-fno-honor-nans", "-mno-amdgpu-ieee"],
             "batch.hip": ["-fno-honor-nans", "-mno-amdgpu-ieee"]}
 
 

@@ -334,9 +334,7 @@ static int run_scan(const ts_series &s, int64_t nb, int m4, const ScanPlan &pl, 
   sp.x = pl.xclass ? s.x : nullptr;
   sp.xedges = pl.xclass ? ed : nullptr;
   if (pl.xclass) sp.edges = nullptr;
-  if (g_ev_start && (e = hipEventRecord(g_ev_start, st)) != hipSuccess) return hip_fail(e, "event");
-  if ((e = launch_scan(s.y_dtype, sp, st)) != hipSuccess) return hip_fail(e, "scan");
-  if (g_ev_stop && (e = hipEventRecord(g_ev_stop, st)) != hipSuccess) return hip_fail(e, "event");
+  if ((e = launch_scan(s.y_dtype, sp, st, g_ev_start, g_ev_stop)) != hipSuccess) return hip_fail(e, "scan");
   MergeParams mp;
   mp.n = s.n;
   mp.shift = sp.shift;
@@ -584,7 +582,7 @@ int ts_bin_argminmax(const ts_series *s, const int64_t *edges, int64_t nb, int64
   sp.xedges = nullptr;
   sp.xclass = 0;
   hipError_t e;
-  if ((e = launch_scan(s->y_dtype, sp, st)) != hipSuccess) return hip_fail(e, "scan");
+  if ((e = launch_scan(s->y_dtype, sp, st, g_ev_start, g_ev_stop)) != hipSuccess) return hip_fail(e, "scan");
   MergeParams mp{};
   mp.n = s->n;
   mp.shift = sp.shift;

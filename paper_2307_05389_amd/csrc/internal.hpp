@@ -75,7 +75,9 @@ int vec_width(int dtype);
 hipError_t launch_edges_x(const void *x, int x_dtype, int64_t n, int64_t nb, int64_t *edges,
                           hipStream_t st);
 hipError_t launch_edges_nox(int64_t n, int64_t nb, int64_t *edges, hipStream_t st);
-hipError_t launch_scan(int y_dtype, const ScanParams &p, hipStream_t st);
+// e0/e1 (optional): events stamped with the scan dispatch's start and end.
+hipError_t launch_scan(int y_dtype, const ScanParams &p, hipStream_t st, hipEvent_t e0 = nullptr,
+                       hipEvent_t e1 = nullptr);
 hipError_t launch_merge(const MergeParams &p, hipStream_t st);
 hipError_t launch_compact(const CompactParams &p, hipStream_t st);
 hipError_t launch_binres_to_outputs(const MergeParams &p, int64_t *imin, int64_t *imax,

@@ -16,10 +16,10 @@
 //               (64 bins per wavefront).  Bins that end in the chunk where
 //               they start are final; the segments of straddling bins are
 //               written as (key, index) partials.
-//   k_merge     one wavefront per bin: lexicographic merge of the partials of
-//               a straddling bin, then the bin's sorted distinct selection.
-//   k_compact   one workgroup: exclusive scan of the per-bin counts and the
-//               compaction into strictly increasing indices.
+//
+// The merge of straddling bins and the compaction are in select.hip.
+#include <hip/hip_ext.h>
+
 #include <limits>
 #include <type_traits>
 
@@ -68,231 +68,63 @@ hipError_t launch_edges_x(const void *x, int xdt, int64_t n, int64_t nb, int64_t
   return hipGetLastError();
 }
 
+// With events, the launch goes through hipExtLaunchKernel, which stamps
+// them with the dispatch's own start and end times (no marker packets
+// around the kernel).
+static void launch_k(void (*k)(ScanParams), dim3 grid, dim3 block, size_t lds, hipStream_t st, hipEvent_t e0,
+                     hipEvent_t e1, const ScanParams &p) {
+  if (e0 || e1) {
+    void *args[] = {(void *)&p};
+    (void)hipExtLaunchKernel((const void *)k, grid, block, args, lds, st, e0, e1, 0);
+  } else {
+    hipLaunchKernelGGL(k, grid, block, (uint32_t)lds, st, p);
+  }
+}
+
 // Tile shapes: 16-byte vectors per lane per tile x tiles in flight.
 template <typename T>
-static hipError_t scan_t(const ScanParams &p, hipStream_t st) {
+static hipError_t scan_t(const ScanParams &p, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
   dim3 grid((unsigned)((p.nchunks + 3) / 4)), block(256);
   if (p.stage) {
     const size_t lds = 4 * sizeof(u32x4) * (size_t)staged_lds_vectors(p.chunk, 16 / (int)sizeof(T));
-    k_scan_staged<T><<<grid, block, lds, st>>>(p);
+    launch_k(k_scan_staged<T>, grid, block, lds, st, e0, e1, p);
     return hipGetLastError();
   }
+  void (*k)(ScanParams);
   if (p.xclass) {
     switch (p.variant) {
-      case 0: k_scan_xc<T, 4, 2><<<grid, block, 0, st>>>(p); break;
-      case 1: k_scan_xc<T, 4, 1><<<grid, block, 0, st>>>(p); break;
-      case 2: k_scan_xc<T, 8, 1><<<grid, block, 0, st>>>(p); break;
-      default: k_scan_xc<T, 2, 2><<<grid, block, 0, st>>>(p); break;
+      case 0: k = k_scan_xc<T, 4, 2>; break;
+      case 1: k = k_scan_xc<T, 4, 1>; break;
+      case 2: k = k_scan_xc<T, 8, 1>; break;
+      default: k = k_scan_xc<T, 2, 2>; break;
     }
-    return hipGetLastError();
+  } else {
+    switch (p.variant) {
+      case 0: k = k_scan<T, 4, 2>; break;
+      case 1: k = k_scan<T, 4, 1>; break;
+      case 2: k = k_scan<T, 8, 1>; break;
+      default: k = k_scan<T, 2, 2>; break;
+    }
   }
-  switch (p.variant) {
-    case 0: k_scan<T, 4, 2><<<grid, block, 0, st>>>(p); break;
-    case 1: k_scan<T, 4, 1><<<grid, block, 0, st>>>(p); break;
-    case 2: k_scan<T, 8, 1><<<grid, block, 0, st>>>(p); break;
-    default: k_scan<T, 2, 2><<<grid, block, 0, st>>>(p); break;
-  }
+  launch_k(k, grid, block, 0, st, e0, e1, p);
   return hipGetLastError();
 }
 
-hipError_t launch_scan(int ydt, const ScanParams &p, hipStream_t st) {
+hipError_t launch_scan(int ydt, const ScanParams &p, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
   switch (ydt) {
-    case TS_I8: return scan_t<int8_t>(p, st);
-    case TS_I16: return scan_t<int16_t>(p, st);
-    case TS_I32: return scan_t<int32_t>(p, st);
-    case TS_I64: return scan_t<int64_t>(p, st);
-    case TS_U8: return scan_t<uint8_t>(p, st);
-    case TS_U16: return scan_t<uint16_t>(p, st);
-    case TS_U32: return scan_t<uint32_t>(p, st);
-    case TS_U64: return scan_t<uint64_t>(p, st);
-    case TS_F16: return scan_t<half_t>(p, st);
-    case TS_F32: return scan_t<float>(p, st);
-    case TS_F64: return scan_t<double>(p, st);
+    case TS_I8: return scan_t<int8_t>(p, st, e0, e1);
+    case TS_I16: return scan_t<int16_t>(p, st, e0, e1);
+    case TS_I32: return scan_t<int32_t>(p, st, e0, e1);
+    case TS_I64: return scan_t<int64_t>(p, st, e0, e1);
+    case TS_U8: return scan_t<uint8_t>(p, st, e0, e1);
+    case TS_U16: return scan_t<uint16_t>(p, st, e0, e1);
+    case TS_U32: return scan_t<uint32_t>(p, st, e0, e1);
+    case TS_U64: return scan_t<uint64_t>(p, st, e0, e1);
+    case TS_F16: return scan_t<half_t>(p, st, e0, e1);
+    case TS_F32: return scan_t<float>(p, st, e0, e1);
+    case TS_F64: return scan_t<double>(p, st, e0, e1);
   }
   return hipErrorInvalidValue;
-}
-
-// ------------------------------------------------------------------ merge
-
-// Merge + selection of one bin by one wavefront (writes sel/cnt).
-__device__ inline void merge_one_bin(const MergeParams &p, int64_t bin, int lane) {
-  int64_t s, e;
-  bin_range(p, bin, s, e);
-  if (s >= e) {
-    if (lane == 0) p.cnt[bin] = 0;
-    return;
-  }
-  int64_t imn, imx;
-  merged_bin(p, s, e, bin, lane, imn, imx);
-  if (lane == 0) p.cnt[bin] = bin_selection(s, e, imn, imx, p.m4, p.sel + 4 * bin);
-}
-
-__global__ __launch_bounds__(256) void k_merge(MergeParams p) {
-  const int64_t bin = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (bin < p.nb) merge_one_bin(p, bin, lane_id());
-}
-
-// One bin per thread (bins spanning few chunks).
-__global__ __launch_bounds__(256) void k_merge_lanes(MergeParams p) {
-  const int64_t bin = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (bin >= p.nb) return;
-  int64_t s, e;
-  bin_range(p, bin, s, e);
-  if (s >= e) {
-    p.cnt[bin] = 0;
-    return;
-  }
-  int64_t imn, imx;
-  merged_bin_lane(p, s, e, bin, imn, imx);
-  p.cnt[bin] = bin_selection(s, e, imn, imx, p.m4, p.sel + 4 * bin);
-}
-
-hipError_t launch_merge(const MergeParams &p, hipStream_t st) {
-  if (p.n / p.nb <= kLaneMergeChunks * p.chunk)
-    k_merge_lanes<<<dim3((unsigned)((p.nb + 255) / 256)), dim3(256), 0, st>>>(p);
-  else
-    k_merge<<<dim3((unsigned)((p.nb + 3) / 4)), dim3(256), 0, st>>>(p);
-  return hipGetLastError();
-}
-
-// Per-bin argmin/argmax to caller arrays (-1 for empty bins).
-__global__ __launch_bounds__(256) void k_binres_out(MergeParams p, int64_t *omin, int64_t *omax) {
-  const int lane = lane_id();
-  const int64_t bin = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (bin >= p.nb) return;
-  int64_t s, e;
-  bin_range(p, bin, s, e);
-  int64_t imn = -1, imx = -1;
-  if (s < e) merged_bin(p, s, e, bin, lane, imn, imx);
-  if (lane == 0) {
-    omin[bin] = imn;
-    omax[bin] = imx;
-  }
-}
-
-hipError_t launch_binres_to_outputs(const MergeParams &p, int64_t *imin, int64_t *imax, hipStream_t st) {
-  k_binres_out<<<dim3((unsigned)((p.nb + 3) / 4)), dim3(256), 0, st>>>(p, imin, imax);
-  return hipGetLastError();
-}
-
-// ------------------------------------------------------------------ compact
-
-// Compaction by one workgroup of any size: exclusive scan of the per-bin
-// counts and the strictly increasing output (or 0..all_n-1).
-__device__ void compact_block(const CompactParams &p, int64_t *lds) {
-  const int t = threadIdx.x;
-  int64_t *out = p.out;
-  if (p.all_n >= 0) {
-    for (int64_t i = t; i < p.all_n; i += blockDim.x) out[i] = i;
-    if (t == 0) *p.out_count = p.all_n;
-    return;
-  }
-  const int64_t per = (p.nb + blockDim.x - 1) / blockDim.x;
-  const int64_t b0 = (int64_t)t * per;
-  const int64_t b1 = b0 + per < p.nb ? b0 + per : p.nb;
-  int64_t local = 0;
-  for (int64_t b = b0; b < b1; b++) local += p.cnt[b];
-  int64_t total;
-  int64_t off = block_exclusive_scan(local, lds, total);
-  for (int64_t b = b0; b < b1; b++) {
-    const int64_t k = p.cnt[b];
-    for (int64_t j = 0; j < k; j++) out[off + j] = p.sel[4 * b + j] + p.index_offset;
-    off += k;
-  }
-  if (t == 0) {
-    if (p.endpoints_n > 0) {
-      out[-1] = 0;
-      out[total] = p.endpoints_n - 1;
-      *p.out_count = total + 2;
-    } else {
-      *p.out_count = total;
-    }
-  }
-}
-
-__global__ __launch_bounds__(1024) void k_compact(CompactParams p) {
-  __shared__ int64_t lds[80];
-  compact_block(p, lds);
-}
-
-// out[i] = i for i < all_n, many workgroups.
-__global__ __launch_bounds__(256) void k_fill_all(CompactParams p) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < p.all_n; i += stride) p.out[i] = i;
-  if (blockIdx.x == 0 && threadIdx.x == 0) *p.out_count = p.all_n;
-}
-
-// Multi-workgroup compaction for many bins, in three launches: per-workgroup
-// sums of the counts of kCompactBins bins, one workgroup's exclusive scan of
-// those sums (plus the count and end points), then every workgroup writes its
-// bins' indices from its offset.
-__global__ __launch_bounds__(256) void k_compact_sums(CompactParams p) {
-  __shared__ int64_t lds[80];
-  const int64_t b0 = (int64_t)blockIdx.x * kCompactBins;
-  const int64_t b1 = b0 + kCompactBins < p.nb ? b0 + kCompactBins : p.nb;
-  int64_t local = 0;
-  for (int64_t b = b0 + threadIdx.x; b < b1; b += blockDim.x) local += p.cnt[b];
-  int64_t total;
-  (void)block_exclusive_scan(local, lds, total);
-  if (threadIdx.x == 0) p.bsum[blockIdx.x] = total;
-}
-
-__global__ __launch_bounds__(1024) void k_compact_offsets(CompactParams p, int64_t nblk) {
-  __shared__ int64_t lds[80];
-  int64_t carry = 0;
-  for (int64_t i0 = 0; i0 < nblk; i0 += blockDim.x) {
-    const int64_t i = i0 + threadIdx.x;
-    const int64_t v = i < nblk ? p.bsum[i] : 0;
-    int64_t tot;
-    const int64_t ex = block_exclusive_scan(v, lds, tot);
-    if (i < nblk) p.bsum[i] = carry + ex;
-    carry += tot;
-  }
-  if (threadIdx.x == 0) {
-    if (p.endpoints_n > 0) {
-      p.out[-1] = 0;
-      p.out[carry] = p.endpoints_n - 1;
-      *p.out_count = carry + 2;
-    } else {
-      *p.out_count = carry;
-    }
-  }
-}
-
-__global__ __launch_bounds__(256) void k_compact_write(CompactParams p) {
-  __shared__ int64_t lds[80];
-  constexpr int64_t per = kCompactBins / 256;
-  const int64_t blk_end = (int64_t)(blockIdx.x + 1) * kCompactBins < p.nb ? (int64_t)(blockIdx.x + 1) * kCompactBins : p.nb;
-  const int64_t b0 = (int64_t)blockIdx.x * kCompactBins + (int64_t)threadIdx.x * per;
-  const int64_t b1 = b0 + per < blk_end ? b0 + per : blk_end;
-  int64_t local = 0;
-  for (int64_t b = b0; b < b1; b++) local += p.cnt[b];
-  int64_t total;
-  int64_t off = block_exclusive_scan(local, lds, total) + p.bsum[blockIdx.x];
-  for (int64_t b = b0; b < b1; b++) {
-    const int64_t k = p.cnt[b];
-    for (int64_t j = 0; j < k; j++) p.out[off + j] = p.sel[4 * b + j] + p.index_offset;
-    off += k;
-  }
-}
-
-hipError_t launch_compact(const CompactParams &p, hipStream_t st) {
-  if (p.all_n >= 0) {
-    int64_t blocks = (p.all_n + 1023) / 1024;
-    if (blocks < 1) blocks = 1;
-    if (blocks > 4096) blocks = 4096;
-    k_fill_all<<<dim3((unsigned)blocks), dim3(256), 0, st>>>(p);
-    return hipGetLastError();
-  }
-  if (p.nb <= kCompactSingleMax || !p.bsum) {
-    k_compact<<<dim3(1), dim3(1024), 0, st>>>(p);
-    return hipGetLastError();
-  }
-  const int64_t nblk = compact_blocks(p.nb);
-  k_compact_sums<<<dim3((unsigned)nblk), dim3(256), 0, st>>>(p);
-  k_compact_offsets<<<dim3(1), dim3(1024), 0, st>>>(p, nblk);
-  k_compact_write<<<dim3((unsigned)nblk), dim3(256), 0, st>>>(p);
-  return hipGetLastError();
 }
 
 }  // namespace tsds

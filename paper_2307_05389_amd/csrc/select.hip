@@ -1,0 +1,200 @@
+// select.hip -- per-bin selection and compaction after the argmin/argmax
+// scan (scan.hip):
+//
+//   k_merge     one wavefront per bin: lexicographic merge of the partials of
+//               a straddling bin, then the bin's sorted distinct selection.
+//   k_compact   one workgroup: exclusive scan of the per-bin counts and the
+//               compaction into strictly increasing indices.
+#include <limits>
+#include <type_traits>
+
+#include "common.hpp"
+#include "internal.hpp"
+#include "scan_core.hpp"
+
+namespace tsds {
+
+// ------------------------------------------------------------------ merge
+
+// Merge + selection of one bin by one wavefront (writes sel/cnt).
+__device__ inline void merge_one_bin(const MergeParams &p, int64_t bin, int lane) {
+  int64_t s, e;
+  bin_range(p, bin, s, e);
+  if (s >= e) {
+    if (lane == 0) p.cnt[bin] = 0;
+    return;
+  }
+  int64_t imn, imx;
+  merged_bin(p, s, e, bin, lane, imn, imx);
+  if (lane == 0) p.cnt[bin] = bin_selection(s, e, imn, imx, p.m4, p.sel + 4 * bin);
+}
+
+__global__ __launch_bounds__(256) void k_merge(MergeParams p) {
+  const int64_t bin = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (bin < p.nb) merge_one_bin(p, bin, lane_id());
+}
+
+// One bin per thread (bins spanning few chunks).
+__global__ __launch_bounds__(256) void k_merge_lanes(MergeParams p) {
+  const int64_t bin = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (bin >= p.nb) return;
+  int64_t s, e;
+  bin_range(p, bin, s, e);
+  if (s >= e) {
+    p.cnt[bin] = 0;
+    return;
+  }
+  int64_t imn, imx;
+  merged_bin_lane(p, s, e, bin, imn, imx);
+  p.cnt[bin] = bin_selection(s, e, imn, imx, p.m4, p.sel + 4 * bin);
+}
+
+hipError_t launch_merge(const MergeParams &p, hipStream_t st) {
+  if (p.n / p.nb <= kLaneMergeChunks * p.chunk)
+    k_merge_lanes<<<dim3((unsigned)((p.nb + 255) / 256)), dim3(256), 0, st>>>(p);
+  else
+    k_merge<<<dim3((unsigned)((p.nb + 3) / 4)), dim3(256), 0, st>>>(p);
+  return hipGetLastError();
+}
+
+// Per-bin argmin/argmax to caller arrays (-1 for empty bins).
+__global__ __launch_bounds__(256) void k_binres_out(MergeParams p, int64_t *omin, int64_t *omax) {
+  const int lane = lane_id();
+  const int64_t bin = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (bin >= p.nb) return;
+  int64_t s, e;
+  bin_range(p, bin, s, e);
+  int64_t imn = -1, imx = -1;
+  if (s < e) merged_bin(p, s, e, bin, lane, imn, imx);
+  if (lane == 0) {
+    omin[bin] = imn;
+    omax[bin] = imx;
+  }
+}
+
+hipError_t launch_binres_to_outputs(const MergeParams &p, int64_t *imin, int64_t *imax, hipStream_t st) {
+  k_binres_out<<<dim3((unsigned)((p.nb + 3) / 4)), dim3(256), 0, st>>>(p, imin, imax);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ compact
+
+// Compaction by one workgroup of any size: exclusive scan of the per-bin
+// counts and the strictly increasing output (or 0..all_n-1).
+__device__ void compact_block(const CompactParams &p, int64_t *lds) {
+  const int t = threadIdx.x;
+  int64_t *out = p.out;
+  if (p.all_n >= 0) {
+    for (int64_t i = t; i < p.all_n; i += blockDim.x) out[i] = i;
+    if (t == 0) *p.out_count = p.all_n;
+    return;
+  }
+  const int64_t per = (p.nb + blockDim.x - 1) / blockDim.x;
+  const int64_t b0 = (int64_t)t * per;
+  const int64_t b1 = b0 + per < p.nb ? b0 + per : p.nb;
+  int64_t local = 0;
+  for (int64_t b = b0; b < b1; b++) local += p.cnt[b];
+  int64_t total;
+  int64_t off = block_exclusive_scan(local, lds, total);
+  for (int64_t b = b0; b < b1; b++) {
+    const int64_t k = p.cnt[b];
+    for (int64_t j = 0; j < k; j++) out[off + j] = p.sel[4 * b + j] + p.index_offset;
+    off += k;
+  }
+  if (t == 0) {
+    if (p.endpoints_n > 0) {
+      out[-1] = 0;
+      out[total] = p.endpoints_n - 1;
+      *p.out_count = total + 2;
+    } else {
+      *p.out_count = total;
+    }
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_compact(CompactParams p) {
+  __shared__ int64_t lds[80];
+  compact_block(p, lds);
+}
+
+// out[i] = i for i < all_n, many workgroups.
+__global__ __launch_bounds__(256) void k_fill_all(CompactParams p) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < p.all_n; i += stride) p.out[i] = i;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *p.out_count = p.all_n;
+}
+
+// Multi-workgroup compaction for many bins, in three launches: per-workgroup
+// sums of the counts of kCompactBins bins, one workgroup's exclusive scan of
+// those sums (plus the count and end points), then every workgroup writes its
+// bins' indices from its offset.
+__global__ __launch_bounds__(256) void k_compact_sums(CompactParams p) {
+  __shared__ int64_t lds[80];
+  const int64_t b0 = (int64_t)blockIdx.x * kCompactBins;
+  const int64_t b1 = b0 + kCompactBins < p.nb ? b0 + kCompactBins : p.nb;
+  int64_t local = 0;
+  for (int64_t b = b0 + threadIdx.x; b < b1; b += blockDim.x) local += p.cnt[b];
+  int64_t total;
+  (void)block_exclusive_scan(local, lds, total);
+  if (threadIdx.x == 0) p.bsum[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(1024) void k_compact_offsets(CompactParams p, int64_t nblk) {
+  __shared__ int64_t lds[80];
+  int64_t carry = 0;
+  for (int64_t i0 = 0; i0 < nblk; i0 += blockDim.x) {
+    const int64_t i = i0 + threadIdx.x;
+    const int64_t v = i < nblk ? p.bsum[i] : 0;
+    int64_t tot;
+    const int64_t ex = block_exclusive_scan(v, lds, tot);
+    if (i < nblk) p.bsum[i] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) {
+    if (p.endpoints_n > 0) {
+      p.out[-1] = 0;
+      p.out[carry] = p.endpoints_n - 1;
+      *p.out_count = carry + 2;
+    } else {
+      *p.out_count = carry;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_compact_write(CompactParams p) {
+  __shared__ int64_t lds[80];
+  constexpr int64_t per = kCompactBins / 256;
+  const int64_t blk_end = (int64_t)(blockIdx.x + 1) * kCompactBins < p.nb ? (int64_t)(blockIdx.x + 1) * kCompactBins : p.nb;
+  const int64_t b0 = (int64_t)blockIdx.x * kCompactBins + (int64_t)threadIdx.x * per;
+  const int64_t b1 = b0 + per < blk_end ? b0 + per : blk_end;
+  int64_t local = 0;
+  for (int64_t b = b0; b < b1; b++) local += p.cnt[b];
+  int64_t total;
+  int64_t off = block_exclusive_scan(local, lds, total) + p.bsum[blockIdx.x];
+  for (int64_t b = b0; b < b1; b++) {
+    const int64_t k = p.cnt[b];
+    for (int64_t j = 0; j < k; j++) p.out[off + j] = p.sel[4 * b + j] + p.index_offset;
+    off += k;
+  }
+}
+
+hipError_t launch_compact(const CompactParams &p, hipStream_t st) {
+  if (p.all_n >= 0) {
+    int64_t blocks = (p.all_n + 1023) / 1024;
+    if (blocks < 1) blocks = 1;
+    if (blocks > 4096) blocks = 4096;
+    k_fill_all<<<dim3((unsigned)blocks), dim3(256), 0, st>>>(p);
+    return hipGetLastError();
+  }
+  if (p.nb <= kCompactSingleMax || !p.bsum) {
+    k_compact<<<dim3(1), dim3(1024), 0, st>>>(p);
+    return hipGetLastError();
+  }
+  const int64_t nblk = compact_blocks(p.nb);
+  k_compact_sums<<<dim3((unsigned)nblk), dim3(256), 0, st>>>(p);
+  k_compact_offsets<<<dim3(1), dim3(1024), 0, st>>>(p, nblk);
+  k_compact_write<<<dim3((unsigned)nblk), dim3(256), 0, st>>>(p);
+  return hipGetLastError();
+}
+
+}  // namespace tsds
