@@ -117,7 +117,7 @@ struct LttbParams {
 // in full) and kHullLane hull points per lane segment.
 constexpr int64_t kHullMinBucket = 512;
 constexpr int kHullCand = 64;
-constexpr int kHullLane = 20;
+constexpr int kHullLane = 24;
 
 hipError_t launch_lttb_centres(const LttbParams &p, hipStream_t st);
 hipError_t launch_lttb_hull(const LttbParams &p, hipStream_t st);

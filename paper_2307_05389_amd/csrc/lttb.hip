@@ -34,6 +34,83 @@
 
 namespace tsds {
 
+// ---------------------------------------------------------------- raw batches
+
+// Raw bits of elements j0 .. j0 + B - 1 (clamped to jmax) of an array of
+// es-byte elements, loaded back to back and converted later, so the loads
+// stay in flight while earlier data is used.
+template <int B, typename R>
+__device__ inline void load_raw(const void *a, int es, int64_t j0, int64_t jmax, R (&r)[B]) {
+  switch (es) {
+    case 1:
+#pragma unroll
+      for (int u = 0; u < B; u++) r[u] = ((const uint8_t *)a)[j0 + u < jmax ? j0 + u : jmax];
+      break;
+    case 2:
+#pragma unroll
+      for (int u = 0; u < B; u++) r[u] = ((const uint16_t *)a)[j0 + u < jmax ? j0 + u : jmax];
+      break;
+    case 4:
+#pragma unroll
+      for (int u = 0; u < B; u++) r[u] = ((const uint32_t *)a)[j0 + u < jmax ? j0 + u : jmax];
+      break;
+    default:
+      if constexpr (sizeof(R) == 8) {
+#pragma unroll
+        for (int u = 0; u < B; u++) r[u] = ((const uint64_t *)a)[j0 + u < jmax ? j0 + u : jmax];
+      }
+      break;
+  }
+}
+
+// Raw bits as the doubles the walk uses (dbl_val), one dtype switch per batch.
+template <int B, typename R>
+__device__ inline void convert_raw(const R (&r)[B], int dt, double (&out)[B]) {
+  switch (dt) {
+#define TS_RAW_CVT(code, expr)                                   \
+  case code:                                                     \
+    _Pragma("unroll") for (int u = 0; u < B; u++) out[u] = expr; \
+    break;
+    TS_RAW_CVT(TS_I8, (double)(int8_t)(uint8_t)r[u])
+    TS_RAW_CVT(TS_U8, (double)(uint8_t)r[u])
+    TS_RAW_CVT(TS_I16, (double)(int16_t)(uint16_t)r[u])
+    TS_RAW_CVT(TS_U16, (double)(uint16_t)r[u])
+    TS_RAW_CVT(TS_F16, (double)(float)__builtin_bit_cast(_Float16, (uint16_t)r[u]))
+    TS_RAW_CVT(TS_F32, (double)__builtin_bit_cast(float, (uint32_t)r[u]))
+    TS_RAW_CVT(TS_I32, (double)(int32_t)(uint32_t)r[u])
+    TS_RAW_CVT(TS_U32, (double)(uint32_t)r[u])
+    TS_RAW_CVT(TS_I64, (double)(int64_t)(uint64_t)r[u])
+    TS_RAW_CVT(TS_U64, (double)(uint64_t)r[u])
+    default:
+#pragma unroll
+      for (int u = 0; u < B; u++) out[u] = __builtin_bit_cast(double, (uint64_t)r[u]);
+      break;
+#undef TS_RAW_CVT
+  }
+}
+
+// Exact sum of the raw integer elements j0 + u < hi of a batch, added to acc.
+template <int B>
+__device__ inline void add_int_raw(const uint64_t (&r)[B], int dt, int64_t j0, int64_t hi, __int128 &acc) {
+  switch (dt) {
+#define TS_RAW_INT(code, expr)                                               \
+  case code:                                                                 \
+    _Pragma("unroll") for (int u = 0; u < B; u++) if (j0 + u < hi) acc += expr; \
+    break;
+    TS_RAW_INT(TS_I8, (__int128)(int8_t)(uint8_t)r[u])
+    TS_RAW_INT(TS_U8, (__int128)(uint8_t)r[u])
+    TS_RAW_INT(TS_I16, (__int128)(int16_t)(uint16_t)r[u])
+    TS_RAW_INT(TS_U16, (__int128)(uint16_t)r[u])
+    TS_RAW_INT(TS_I32, (__int128)(int32_t)(uint32_t)r[u])
+    TS_RAW_INT(TS_U32, (__int128)(uint32_t)r[u])
+    TS_RAW_INT(TS_I64, (__int128)(int64_t)r[u])
+    TS_RAW_INT(TS_U64, (__int128)(uint64_t)r[u])
+    default:
+      break;
+#undef TS_RAW_INT
+  }
+}
+
 // ---------------------------------------------------------------- centres
 
 // Sums over a contiguous range [lo, hi) of one array (no index list), with
@@ -130,17 +207,35 @@ __global__ __launch_bounds__(256) void k_centres(LttbParams p) {
 }
 
 // Centres of a plain series with long buckets, one wavefront per bucket.
-// Integer coordinates: each lane sums its share exactly and lane 0 adds the
-// 64 partial sums (exact, so the order is free).  Float coordinates: the
-// wavefront copies the bucket to LDS a tile at a time (coalesced) and lane 0
-// (Y) / lane 1 (X) add the tile strictly in index order, as the sequential
-// loop does.  The index coordinate has a closed form.
-constexpr int kCentreTile = 1024;
+// The wavefront reads the bucket a tile at a time (kCentreBatch consecutive
+// points per lane; the loads of the next tile are in flight while the current
+// one is added).  Integer coordinates: every lane adds its points exactly in
+// 128 bits and lane 0 adds the 64 partial sums (exact, so the order is free).
+// Float coordinates: the tile is staged in LDS as doubles (converted by all
+// lanes) and lane 0 adds it strictly in index order, as the sequential loop
+// does.  The index coordinate has a
+// closed form.
+constexpr int kCentreBatch = 16;
+constexpr int kCentreTile = 64 * kCentreBatch;
 
 __device__ inline bool float_dtype(int dt) { return dt == TS_F16 || dt == TS_F32 || dt == TS_F64; }
 
+// acc + b[0] + b[1] + ... + b[cnt-1], left to right.
+__device__ inline double seq_sum(const double *b, int cnt, double acc) {
+  int j = 0;
+  for (; j + 8 <= cnt; j += 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; u++) v[u] = b[j + u];
+#pragma unroll
+    for (int u = 0; u < 8; u++) acc += v[u];
+  }
+  for (; j < cnt; j++) acc += b[j];
+  return acc;
+}
+
 __global__ __launch_bounds__(64) void k_centres_wave(LttbParams p) {
-  __shared__ double tile[2][kCentreTile];
+  __shared__ double tile[2][kCentreTile];  // float coordinates as doubles: [0] Y, [1] X
   __shared__ __int128 part[2][64];
   const int lane = threadIdx.x;
   const int64_t m = p.m, nb = p.n_out - 2;
@@ -154,51 +249,66 @@ __global__ __launch_bounds__(64) void k_centres_wave(LttbParams p) {
   }
   const int64_t lo = bucket_start(k + 1, m, nb), hi = bucket_start(k + 2, m, nb);
   const double cnt = (double)(hi - lo);
-  const bool fx = p.x_dtype != TS_NONE && float_dtype(p.x_dtype), fy = float_dtype(p.y_dtype);
-  // exact integer parts (lane shares, then lane 0 / lane 1 add them up)
+  const bool hx = p.x_dtype != TS_NONE;
+  const bool fx = hx && float_dtype(p.x_dtype), fy = float_dtype(p.y_dtype);
+  const int ysb = elem_bytes(p.y_dtype), xsb = hx ? elem_bytes(p.x_dtype) : 0;
   __int128 ix = 0, iy = 0;
-  const bool ex = p.x_dtype != TS_NONE && !fx;
-  if (ex || !fy) {
-    for (int64_t j = lo + lane; j < hi; j += 64) {
-      if (ex) ix += int_val(p.x, p.x_dtype, j);
-      if (!fy) iy += int_val(p.y, p.y_dtype, j);
+  double sx = 0.0, sy = 0.0;
+  const int off = lane * kCentreBatch;
+  uint64_t ry[kCentreBatch], rx[kCentreBatch];
+  load_raw(p.y, ysb, lo + off, hi - 1, ry);
+  if (hx) load_raw(p.x, xsb, lo + off, hi - 1, rx);
+  for (int64_t t0 = lo; t0 < hi; t0 += kCentreTile) {
+    const int64_t j0 = t0 + off;
+    if (fy) {
+      double v[kCentreBatch];
+      convert_raw(ry, p.y_dtype, v);  // converted by all lanes, added by one
+#pragma unroll
+      for (int u = 0; u < kCentreBatch; u++) tile[0][off + u] = v[u];
+    } else {
+      add_int_raw(ry, p.y_dtype, j0, hi, iy);
     }
+    if (fx) {
+      double v[kCentreBatch];
+      convert_raw(rx, p.x_dtype, v);
+#pragma unroll
+      for (int u = 0; u < kCentreBatch; u++) tile[1][off + u] = v[u];
+    } else if (hx) {
+      add_int_raw(rx, p.x_dtype, j0, hi, ix);
+    }
+    __syncthreads();
+    load_raw(p.y, ysb, j0 + kCentreTile, hi - 1, ry);
+    if (hx) load_raw(p.x, xsb, j0 + kCentreTile, hi - 1, rx);
+    const int c = (int)(hi - t0 < kCentreTile ? hi - t0 : kCentreTile);
+    if (lane == 0) {
+      if (fy) sy = seq_sum(tile[0], c, sy);
+      if (fx) sx = seq_sum(tile[1], c, sx);
+    }
+    __syncthreads();
   }
   part[0][lane] = ix;
   part[1][lane] = iy;
-  // sequential float sums through LDS tiles
-  double sx = 0.0, sy = 0.0;
-  if (fx || fy) {
-    for (int64_t t0 = lo; t0 < hi; t0 += kCentreTile) {
-      const int64_t t1 = t0 + kCentreTile < hi ? t0 + kCentreTile : hi;
-      for (int64_t j = t0 + lane; j < t1; j += 64) {
-        if (fy) tile[0][j - t0] = dbl_val(p.y, p.y_dtype, j);
-        if (fx) tile[1][j - t0] = dbl_val(p.x, p.x_dtype, j);
-      }
-      __syncthreads();
-      if ((lane == 0 && fy) || (lane == 1 && fx)) {
-        const double *tv = tile[lane];
-        double acc = lane == 0 ? sy : sx;
-        for (int64_t j = 0; j < t1 - t0; j++) acc += tv[j];
-        if (lane == 0) sy = acc; else sx = acc;
-      }
-      __syncthreads();
-    }
-  }
   __syncthreads();
-  if (lane < 2) {
-    double mean;
-    const int c = lane;  // 0: y, 1: x
-    if (c == 1 && p.x_dtype == TS_NONE) {
-      mean = i128_to_double(((__int128)lo + (__int128)hi - 1) * (__int128)(hi - lo) / 2) / cnt;
-    } else if (c == 0 ? fy : fx) {
-      mean = (c == 0 ? sy : sx) / cnt;
+  if (lane == 0) {
+    double my, mx;
+    if (fy) {
+      my = sy / cnt;
     } else {
-      __int128 s = 0;
-      for (int i = 0; i < 64; i++) s += part[c == 0 ? 1 : 0][i];
-      mean = i128_to_double(s) / cnt;
+      __int128 t = 0;
+      for (int i = 0; i < 64; i++) t += part[1][i];
+      my = i128_to_double(t) / cnt;
     }
-    if (c == 0) p.cy[k] = mean; else p.cx[k] = mean;
+    if (!hx) {
+      mx = i128_to_double(((__int128)lo + (__int128)hi - 1) * (__int128)(hi - lo) / 2) / cnt;
+    } else if (fx) {
+      mx = sx / cnt;
+    } else {
+      __int128 t = 0;
+      for (int i = 0; i < 64; i++) t += part[0][i];
+      mx = i128_to_double(t) / cnt;
+    }
+    p.cy[k] = my;
+    p.cx[k] = mx;
   }
 }
 
@@ -319,8 +429,9 @@ hipError_t launch_lttb_seq(const LttbParams &p, hipStream_t st) {
 // the absolute value of a linear function of b's coordinates, so over a
 // bucket its maximum is reached at a vertex of the bucket's convex hull.  The
 // hulls do not depend on the walk: k_lttb_hull builds every bucket's hull in
-// parallel (one wavefront per bucket: each lane a monotone chain over its
-// slice, then one lane per chain merges the 64 slices), and the walk only
+// parallel (one wavefront per bucket: lanes 0-31 run the upper monotone
+// chains of 32 slices and lanes 32-63 the lower ones, 16 lanes merge groups
+// of 4 slices, one lane per chain merges the groups), and the walk only
 // evaluates the hull vertices.
 //
 // First-occurrence ties: the points reaching the maximum form a vertex or a
@@ -339,266 +450,302 @@ __device__ inline double cross3(double ox, double oy, double ax, double ay, doub
 
 // Turn pops per point in the branch-free slice chains.
 constexpr int kHullPops = 3;
+// Slices per bucket: lane l < 32 builds the upper chain of slice l, lane
+// 32 + l the lower chain of the same slice.
+constexpr int kHullSlices = 32;
 
-// Monotone chain over points added in index order (offsets from the bucket
-// start `lo`), its stack (offset, Y and, with x, X) in LDS; without x, X is
-// the index lo + offset.  upper: the upper hull (keeps clockwise turns), else
-// the lower hull.
-template <bool HX>
+// Chain entries keep Y as a float when every value of the series' dtype is a
+// float (exact), else as a double.
+__host__ __device__ constexpr bool hull_float_y(int dt) {
+  return dt == TS_I8 || dt == TS_U8 || dt == TS_I16 || dt == TS_U16 || dt == TS_F16 || dt == TS_F32;
+}
+
+// A chain entry: offset from the bucket start, Y and, with x, X (without x,
+// X is the offset).
+template <bool HX, typename YS>
+struct HullEntry {
+  int32_t o;
+  YS y;
+  double x;
+};
+template <typename YS>
+struct HullEntry<false, YS> {
+  int32_t o;
+  YS y;
+};
+
+// Monotone chain over points added in index order, its stack in LDS (entry i
+// at [i * stride], so the stacks of a wavefront's lanes interleave).  sg = +1
+// keeps the upper hull (pops on clockwise or collinear turns), sg = -1 the
+// lower hull; negating a product or a Y is exact, so both use one test.
+template <bool HX, typename YS>
 struct HullChain {
-  int32_t *so;
-  double *sx, *sy;
-  int64_t lo;
-  int n, cap, stride;  // entry i at [i * stride] (lane stacks interleave, stride 64)
-  bool upper, over;
+  using E = HullEntry<HX, YS>;
+  E *s;
+  int n, cap, stride;
+  double sg;
+  bool over;
   // the top two entries are also kept in registers: a push reads no LDS and a
   // pop reads only the entry that becomes second
   double tx, ty, ux, uy;
-  __device__ HullChain(int32_t *o, double *x, double *y, int64_t lo_, int capacity, int str, bool up)
-      : so(o), sx(x), sy(y), lo(lo_), n(0), cap(capacity), stride(str), upper(up), over(false), tx(0), ty(0),
-        ux(0), uy(0) {}
-  // without x the X coordinate is the offset from the bucket start (cross
-  // products of small integers, identical to those of the absolute index)
-  __device__ double X(int i) const { return HX ? sx[i * stride] : (double)so[i * stride]; }
-  __device__ double Y(int i) const { return sy[i * stride]; }
+  __device__ HullChain(E *st, int capacity, int str, bool upper)
+      : s(st), n(0), cap(capacity), stride(str), sg(upper ? 1.0 : -1.0), over(false), tx(0), ty(0), ux(0), uy(0) {}
+  __device__ static double ex(const E &e) {
+    if constexpr (HX)
+      return e.x;
+    else
+      return (double)e.o;
+  }
+  __device__ E at(int i) const { return s[i * stride]; }
+  __device__ void put(int i, int32_t o, double x, double y) {
+    E e;
+    e.o = o;
+    e.y = (YS)y;  // exact: Y is a value of the series' dtype
+    if constexpr (HX) e.x = x;
+    s[i * stride] = e;
+  }
   __device__ void pop() {
     n--;
     tx = ux;
     ty = uy;
     if (n >= 2) {
-      ux = X(n - 2);
-      uy = Y(n - 2);
+      const E v = at(n - 2);
+      ux = ex(v);
+      uy = (double)v.y;
     }
   }
-  // Branch-free variant for whole wavefronts of independent chains: at most
-  // one pop for a repeated X and kHullPops turn pops per point (further pops
-  // are skipped, so the stack may keep extra points but never loses a hull
+  // Branch-free variant for a wavefront of independent chains: at most one
+  // pop for a repeated X and kHullPops turn pops per point (further pops are
+  // skipped, so the stack may keep extra points but never loses a hull
   // vertex: every pop is justified by two points of the set).  The entries
-  // that may become second are read from LDS up front, in one round trip.
+  // that may become second are read from LDS up front, in one round trip;
+  // the turn test of every state the pops can reach is computed at once (the
+  // pops taken are the leading run of passed tests), and the point is always
+  // stored, at the slot above the top (slot cap, a spare one, when the stack
+  // is full), so lanes branch only when a stack fills up: it is then rebuilt
+  // with the exact chain (compact) and marked over only if still full.
   __device__ void add_bounded(int32_t j, double xj, double yj) {
     constexpr int K = HX ? kHullPops + 1 : kHullPops;  // without x no X repeats
-    // ex/ey[i]: the entry that becomes second after i + 1 pops; popping
-    // shifts this window (selects only, no indexed registers)
-    double ex[K], ey[K];
+    // state i (after i pops): second entry U[i], top T[i]; U[i] = entry n-2-i
+    double Ux[K + 1], Uy[K + 1];
+    Ux[0] = ux;
+    Uy[0] = uy;
 #pragma unroll
     for (int i = 0; i < K; i++) {
       const int e = n - 3 - i >= 0 ? n - 3 - i : 0;
-      ex[i] = X(e);
-      ey[i] = Y(e);
+      const E v = at(e);
+      Ux[i + 1] = ex(v);
+      Uy[i + 1] = (double)v.y;
+    }
+    bool tp[K];  // turn pop from state i
+#pragma unroll
+    for (int i = 0; i < K; i++) {
+      const double Tx = i == 0 ? tx : Ux[i - 1], Ty = i == 0 ? ty : Uy[i - 1];
+      const double c = sg * cross3(Ux[i], Uy[i], Tx, Ty, xj, yj);  // computed by every lane, no branch
+      tp[i] = (n - i >= 2) & (c >= 0.0);
     }
     const bool same = HX && n > 0 && xj == tx;
-    const bool act = !over && !(same && (upper ? !(yj > ty) : !(yj < ty)));
-    auto cond_pop = [&](bool pp) {
-      if (pp) {
-        n--;
-        tx = ux;
-        ty = uy;
-        ux = ex[0];
-        uy = ey[0];
+    const bool act = !over && !(same && !(sg * yj > sg * ty));
+    const bool sp = HX && act && same;  // the repeated-X pop
+    int k = sp ? 1 : 0;
+    bool go = act;
 #pragma unroll
-        for (int i = 0; i + 1 < K; i++) {
-          ex[i] = ex[i + 1];
-          ey[i] = ey[i + 1];
+    for (int q = 0; q < kHullPops; q++) {
+      go = go && (HX && sp ? tp[q + 1 < K ? q + 1 : K - 1] : tp[q]);
+      k += go ? 1 : 0;
+    }
+    // top after the pops: T[k] (T[0] = t, T[i] = U[i-1])
+    double nx = tx, ny = ty;
+#pragma unroll
+    for (int i = 1; i <= K; i++) {
+      nx = k == i ? Ux[i - 1] : nx;
+      ny = k == i ? Uy[i - 1] : ny;
+    }
+    const int m = n - k;
+    if (act && m == cap) {  // full (no pop taken): rare, the lane branches off
+      compact();
+      add(j, xj, yj);
+      return;
+    }
+    put(m < cap ? m : cap, j, xj, yj);  // !act with a full stack: the spare slot
+    n = act ? m + 1 : m;
+    // without a push no pop was taken: the top two stay as they are
+    ux = act ? nx : ux;
+    uy = act ? ny : uy;
+    tx = act ? xj : tx;
+    ty = act ? yj : ty;
+  }
+  // The exact chain over the stored entries, in place: the stack becomes the
+  // hull of the points added so far (the bounded pops may have kept extra
+  // points; the stored X are strictly increasing, so no repeated X is met).
+  __device__ void compact() {
+    int w = 0;
+    double ax = 0, ay = 0, bx = 0, by = 0;  // second and top of the rebuilt stack
+    for (int r = 0; r < n; r++) {
+      const E v = at(r);
+      const double xr = ex(v), yr = (double)v.y;
+      while (w >= 2 && sg * cross3(ax, ay, bx, by, xr, yr) >= 0.0) {
+        w--;
+        bx = ax;
+        by = ay;
+        if (w >= 2) {
+          const E q = at(w - 2);
+          ax = ex(q);
+          ay = (double)q.y;
         }
       }
-    };
-    cond_pop(act && same);
-#pragma unroll
-    for (int s = 0; s < kHullPops; s++) {
-      const double c = cross3(ux, uy, tx, ty, xj, yj);
-      cond_pop(act && n >= 2 && (upper ? c >= 0.0 : c <= 0.0));
+      s[w * stride] = v;
+      w++;
+      ax = bx;
+      ay = by;
+      bx = xr;
+      by = yr;
     }
-    if (act && n == cap) over = true;
-    if (act && !over) {
-      so[n * stride] = j;
-      if (HX) sx[n * stride] = xj;
-      sy[n * stride] = yj;
-      n++;
-      ux = tx;
-      uy = ty;
-      tx = xj;
-      ty = yj;
-    }
+    n = w;
+    tx = bx;
+    ty = by;
+    ux = ax;
+    uy = ay;
   }
+  // Exact monotone chain step (merges and re-reads).
   __device__ void add(int32_t j, double xj, double yj) {
     if (over) return;
-    if (n > 0 && xj == tx) {  // same X as the top: keep the first highest (lowest)
-      if (upper ? !(yj > ty) : !(yj < ty)) return;
+    if (HX && n > 0 && xj == tx) {  // same X as the top: keep the first highest (lowest)
+      if (!(sg * yj > sg * ty)) return;
       pop();
     }
-    while (n >= 2) {
-      const double c = cross3(ux, uy, tx, ty, xj, yj);
-      if (upper ? c >= 0.0 : c <= 0.0)
-        pop();
-      else
-        break;
-    }
+    while (n >= 2 && sg * cross3(ux, uy, tx, ty, xj, yj) >= 0.0) pop();
     if (n == cap) {
       over = true;
       return;
     }
-    so[n * stride] = j;
-    if (HX) sx[n * stride] = xj;
-    sy[n * stride] = yj;
+    put(n, j, xj, yj);
     n++;
     ux = tx;
     uy = ty;
     tx = xj;
     ty = yj;
   }
+  __device__ void add_entry(const E &v) { add(v.o, ex(v), (double)v.y); }
 };
 
 // Points loaded per lane before they are added (independent loads in flight).
 constexpr int kHullBatch = 16;
 
-// Elements j0 .. j0 + kHullBatch - 1 (clamped to jmax) of a series of dtype
-// dt as the doubles the walk uses (dbl_val): the dtype switch is taken once
-// per batch and the loads inside it are issued back to back.
-template <typename V>
-__device__ inline void batch_as_double(const V *a, int64_t j0, int64_t jmax, double (&out)[kHullBatch]) {
-  V v[kHullBatch];
-#pragma unroll
-  for (int u = 0; u < kHullBatch; u++) v[u] = a[j0 + u < jmax ? j0 + u : jmax];
-#pragma unroll
-  for (int u = 0; u < kHullBatch; u++) out[u] = (double)v[u];
-}
-
-__device__ inline void load_batch(const void *a, int dt, int64_t j0, int64_t jmax, double (&out)[kHullBatch]) {
-  switch (dt) {
-    case TS_I8: batch_as_double((const int8_t *)a, j0, jmax, out); break;
-    case TS_I16: batch_as_double((const int16_t *)a, j0, jmax, out); break;
-    case TS_I32: batch_as_double((const int32_t *)a, j0, jmax, out); break;
-    case TS_I64: batch_as_double((const int64_t *)a, j0, jmax, out); break;
-    case TS_U8: batch_as_double((const uint8_t *)a, j0, jmax, out); break;
-    case TS_U16: batch_as_double((const uint16_t *)a, j0, jmax, out); break;
-    case TS_U32: batch_as_double((const uint32_t *)a, j0, jmax, out); break;
-    case TS_U64: batch_as_double((const uint64_t *)a, j0, jmax, out); break;
-    case TS_F16: {
-      uint16_t v[kHullBatch];
-      const uint16_t *h = (const uint16_t *)a;
-#pragma unroll
-      for (int u = 0; u < kHullBatch; u++) v[u] = h[j0 + u < jmax ? j0 + u : jmax];
-#pragma unroll
-      for (int u = 0; u < kHullBatch; u++) out[u] = (double)(float)__builtin_bit_cast(_Float16, v[u]);
-      break;
-    }
-    case TS_F32: batch_as_double((const float *)a, j0, jmax, out); break;
-    default: batch_as_double((const double *)a, j0, jmax, out); break;
-  }
-}
-
-// Coordinates of a batch of points lo + j0 + u of the series.
-template <bool HX>
-__device__ inline void load_points(const LttbParams &p, int64_t lo, int64_t j0, int64_t jmax,
-                                   double (&xs)[kHullBatch], double (&ys)[kHullBatch]) {
-  load_batch(p.y, p.y_dtype, j0, jmax, ys);
-  if (HX) {
-    load_batch(p.x, p.x_dtype, j0, jmax, xs);
-  } else {
-    const double xb = (double)(j0 - lo);  // offset from the bucket start
-#pragma unroll
-    for (int u = 0; u < kHullBatch; u++) xs[u] = xb + (double)u;
-  }
-}
-
-template <bool HX, bool HC>
-__device__ void feed_raw(const LttbParams &p, int64_t lo, int64_t a, int64_t b, HullChain<HC> &h) {
+// Points lo + a .. lo + b - 1 added one by one with the exact chain (the
+// re-read of a slice or group whose chain overflowed), loaded in batches.
+template <bool HX, typename YS>
+__device__ void feed_raw(const LttbParams &p, int64_t lo, int64_t a, int64_t b, HullChain<HX, YS> &h) {
+  using RY = typename std::conditional<sizeof(YS) == 4, uint32_t, uint64_t>::type;
+  const int ysb = (int)elem_bytes(p.y_dtype), xsb = HX ? (int)elem_bytes(p.x_dtype) : 0;
   for (int64_t j0 = a; j0 < b; j0 += kHullBatch) {
-    double xs[kHullBatch], ys[kHullBatch];
-    load_points<HX>(p, lo, lo + j0, lo + b - 1, xs, ys);
-#pragma unroll
-    for (int u = 0; u < kHullBatch; u++)
-      if (j0 + u < b) h.add((int32_t)(j0 + u), xs[u], ys[u]);
+    RY ry[kHullBatch];
+    uint64_t rx[HX ? kHullBatch : 1];
+    double ys[kHullBatch], xs[kHullBatch];
+    load_raw(p.y, ysb, lo + j0, lo + b - 1, ry);
+    if constexpr (HX) load_raw(p.x, xsb, lo + j0, lo + b - 1, rx);
+    convert_raw(ry, p.y_dtype, ys);
+    if constexpr (HX) convert_raw(rx, p.x_dtype, xs);
+    for (int u = 0; u < kHullBatch && j0 + u < b; u++) h.add((int32_t)(j0 + u), HX ? xs[u] : (double)(j0 + u), ys[u]);
   }
 }
 
-// Group chains of the two-level merge: 8 groups of 8 slices per chain kind.
+// Group chains of the two-level merge: 8 groups of 4 slices per chain kind.
 constexpr int kHullGroup = 32;
 
-template <bool HX>
+template <bool HX, typename YS>
 __global__ __launch_bounds__(64) void k_lttb_hull(LttbParams p) {
-  // lane stacks, interleaved: entry i of lane l of chain c at [c][i * 64 + l]
-  __shared__ int32_t so[2][64 * kHullLane];
-  __shared__ double sx[HX ? 2 : 1][HX ? 64 * kHullLane : 1], sy[2][64 * kHullLane];
-  __shared__ int32_t nsl[2][64];
-  // group chains: entry i of group g of chain c at [i * 16 + c * 8 + g]
-  __shared__ int32_t go[16 * kHullGroup];
-  __shared__ double gx[HX ? 16 * kHullGroup : 1], gy[16 * kHullGroup];
+  using E = HullEntry<HX, YS>;
+  using RY = typename std::conditional<sizeof(YS) == 4, uint32_t, uint64_t>::type;
+  // lane stacks: entry i of lane l at [i * 64 + l]; entry kHullLane is the spare slot
+  __shared__ E ls[64 * (kHullLane + 1)];
+  __shared__ int32_t nsl[64];
+  // group chains: entry i of group chain c at [i * 16 + c] (c < 8 upper)
+  __shared__ E gs[16 * kHullGroup];
   __shared__ int32_t ngr[16];
-  __shared__ int32_t mo[2][kHullCand];
-  __shared__ double mx[2][kHullCand], my[2][kHullCand];
+  __shared__ E ms[2][kHullCand];
   __shared__ int32_t mg_n[2];
   const int lane = threadIdx.x;
   const int64_t m = p.m, nb = p.n_out - 2;
   const int64_t k = blockIdx.x;
   const int64_t lo = bucket_start(k, m, nb), hi = bucket_start(k + 1, m, nb);
   const int64_t len = hi - lo;
-  // 1. one slice per lane (slices in index order), points loaded in batches
+  const int ys_bytes = (int)elem_bytes(p.y_dtype), xs_bytes = HX ? (int)elem_bytes(p.x_dtype) : 0;
+  // 1. one chain per lane over its slice, batches of points prefetched
   {
-    const int64_t s0 = len * lane / 64, s1 = len * (lane + 1) / 64;
-    HullChain<HX> up(so[0] + lane, HX ? sx[0] + lane : nullptr, sy[0] + lane, lo, kHullLane, 64, true);
-    HullChain<HX> dn(so[1] + lane, HX ? sx[HX ? 1 : 0] + lane : nullptr, sy[1] + lane, lo, kHullLane, 64, false);
-    for (int64_t j0 = s0; j0 < s1; j0 += kHullBatch) {
-      double xs[kHullBatch], ys[kHullBatch];
-      load_points<HX>(p, lo, lo + j0, lo + s1 - 1, xs, ys);
+    const int sl = lane & (kHullSlices - 1);
+    const int64_t s0 = len * sl / kHullSlices, s1 = len * (sl + 1) / kHullSlices;
+    HullChain<HX, YS> h(ls + lane, kHullLane, 64, lane < kHullSlices);
+    const int64_t full = (len / kHullSlices) / kHullBatch;  // batches every lane has in full
+    RY ry[kHullBatch];
+    uint64_t rx[HX ? kHullBatch : 1];
+    load_raw(p.y, ys_bytes, lo + s0, lo + s1 - 1, ry);
+    if constexpr (HX) load_raw(p.x, xs_bytes, lo + s0, lo + s1 - 1, rx);
+    int64_t j0 = s0;
+    for (int64_t t = 0; t < full; t++, j0 += kHullBatch) {
+      double ys[kHullBatch], xs[kHullBatch];
+      convert_raw(ry, p.y_dtype, ys);
+      if constexpr (HX) convert_raw(rx, p.x_dtype, xs);
+      load_raw(p.y, ys_bytes, lo + j0 + kHullBatch, lo + s1 - 1, ry);
+      if constexpr (HX) load_raw(p.x, xs_bytes, lo + j0 + kHullBatch, lo + s1 - 1, rx);
+      const double xb = (double)j0;  // without x: X of point j0 + u is xb + u, exact
 #pragma unroll
-      for (int u = 0; u < kHullBatch; u++) {
-        if (j0 + u < s1) {
-          up.add_bounded((int32_t)(j0 + u), xs[u], ys[u]);
-          dn.add_bounded((int32_t)(j0 + u), xs[u], ys[u]);
-        }
-      }
+      for (int u = 0; u < kHullBatch; u++) h.add_bounded((int32_t)(j0 + u), HX ? xs[u] : xb + (double)u, ys[u]);
     }
-    nsl[0][lane] = up.over ? -1 : up.n;  // -1: the slice's points are re-read
-    nsl[1][lane] = dn.over ? -1 : dn.n;
+    for (; j0 < s1; j0 += kHullBatch) {  // the rest of the slice (lengths differ by one between lanes)
+      double ys[kHullBatch], xs[kHullBatch];
+      convert_raw(ry, p.y_dtype, ys);
+      if constexpr (HX) convert_raw(rx, p.x_dtype, xs);
+      load_raw(p.y, ys_bytes, lo + j0 + kHullBatch, lo + s1 - 1, ry);
+      if constexpr (HX) load_raw(p.x, xs_bytes, lo + j0 + kHullBatch, lo + s1 - 1, rx);
+      const double xb = (double)j0;
+#pragma unroll
+      for (int u = 0; u < kHullBatch; u++)
+        if (j0 + u < s1) h.add_bounded((int32_t)(j0 + u), HX ? xs[u] : xb + (double)u, ys[u]);
+    }
+    nsl[lane] = h.over ? -1 : h.n;  // -1: the slice's points are re-read
   }
   __syncthreads();
-  // 2. lanes 0-15 merge 8 slices each (lanes 0-7 upper, 8-15 lower); a
+  // 2. lanes 0-15 merge 4 slices each (lanes 0-7 upper, 8-15 lower); a
   //    slice's hull keeps every point of the bucket's hull in the slice
   if (lane < 16) {
-    const int c = lane >> 3, g = lane & 7;
-    HullChain<HX> h(go + lane, HX ? gx + lane : nullptr, gy + lane, lo, kHullGroup, 16, c == 0);
-    for (int sl = 8 * g; sl < 8 * g + 8; sl++) {
-      const int32_t cn = nsl[c][sl];
+    const bool up = lane < 8;
+    const int g = lane & 7;
+    HullChain<HX, YS> h(gs + lane, kHullGroup, 16, up);
+    for (int sl = 4 * g; sl < 4 * g + 4; sl++) {
+      const int src = up ? sl : kHullSlices + sl;
+      const int32_t cn = nsl[src];
       if (cn < 0) {
-        feed_raw<HX>(p, lo, len * sl / 64, len * (sl + 1) / 64, h);
+        feed_raw<HX>(p, lo, len * sl / kHullSlices, len * (sl + 1) / kHullSlices, h);
         continue;
       }
-      for (int e = 0; e < cn; e++) {
-        const int q = e * 64 + sl;
-        h.add(so[c][q], HX ? sx[HX ? c : 0][q] : (double)so[c][q], sy[c][q]);
-      }
+      for (int e = 0; e < cn; e++) h.add_entry(ls[e * 64 + src]);
     }
     ngr[lane] = h.over ? -1 : h.n;
   }
   __syncthreads();
   // 3. lane 0 merges the upper group chains, lane 1 the lower ones
   if (lane < 2) {
-    const int c = lane;
-    HullChain<true> h(mo[c], mx[c], my[c], lo, kHullCand, 1, c == 0);
+    const bool up = lane == 0;
+    HullChain<HX, YS> h(ms[lane], kHullCand, 1, up);
     for (int g = 0; g < 8; g++) {
-      const int gi = c * 8 + g;
+      const int gi = (up ? 0 : 8) + g;
       const int32_t cn = ngr[gi];
       if (cn >= 0) {
-        for (int e = 0; e < cn; e++) {
-          const int q = e * 16 + gi;
-          h.add(go[q], HX ? gx[q] : (double)go[q], gy[q]);
-        }
+        for (int e = 0; e < cn; e++) h.add_entry(gs[e * 16 + gi]);
         continue;
       }
-      for (int sl = 8 * g; sl < 8 * g + 8; sl++) {  // the group's chain overflowed
-        const int32_t sn = nsl[c][sl];
+      for (int sl = 4 * g; sl < 4 * g + 4; sl++) {  // the group's chain overflowed
+        const int src = up ? sl : kHullSlices + sl;
+        const int32_t sn = nsl[src];
         if (sn < 0) {
-          feed_raw<HX>(p, lo, len * sl / 64, len * (sl + 1) / 64, h);
+          feed_raw<HX>(p, lo, len * sl / kHullSlices, len * (sl + 1) / kHullSlices, h);
           continue;
         }
-        for (int e = 0; e < sn; e++) {
-          const int q = e * 64 + sl;
-          h.add(so[c][q], HX ? sx[HX ? c : 0][q] : (double)so[c][q], sy[c][q]);
-        }
+        for (int e = 0; e < sn; e++) h.add_entry(ls[e * 64 + src]);
       }
     }
-    mg_n[c] = h.over ? -1 : h.n;
+    mg_n[lane] = h.over ? -1 : h.n;
   }
   __syncthreads();
   // 4. candidates: the bucket's first point and both chains, in index order
@@ -623,13 +770,13 @@ __global__ __launch_bounds__(64) void k_lttb_hull(LttbParams p) {
       };
       put(0, X_of(p, lo), Y_of(p, lo));
       while (iu < nu || id < nd) {
-        const int32_t a = iu < nu ? mo[0][iu] : INT32_MAX, b = id < nd ? mo[1][id] : INT32_MAX;
+        const int32_t a = iu < nu ? ms[0][iu].o : INT32_MAX, b = id < nd ? ms[1][id].o : INT32_MAX;
         if (a <= b) {
-          put(a, mx[0][iu], my[0][iu]);
+          put(a, HullChain<HX, YS>::ex(ms[0][iu]), (double)ms[0][iu].y);
           iu++;
           if (a == b) id++;
         } else {
-          put(b, mx[1][id], my[1][id]);
+          put(b, HullChain<HX, YS>::ex(ms[1][id]), (double)ms[1][id].y);
           id++;
         }
       }
@@ -641,10 +788,19 @@ __global__ __launch_bounds__(64) void k_lttb_hull(LttbParams p) {
 
 hipError_t launch_lttb_hull(const LttbParams &p, hipStream_t st) {
   const int64_t nb = p.n_out - 2;
-  if (p.x_dtype == TS_NONE)
-    k_lttb_hull<false><<<dim3((unsigned)nb), dim3(64), 0, st>>>(p);
-  else
-    k_lttb_hull<true><<<dim3((unsigned)nb), dim3(64), 0, st>>>(p);
+  const dim3 grid((unsigned)nb), block(64);
+  const bool fy = hull_float_y(p.y_dtype);
+  if (p.x_dtype == TS_NONE) {
+    if (fy)
+      k_lttb_hull<false, float><<<grid, block, 0, st>>>(p);
+    else
+      k_lttb_hull<false, double><<<grid, block, 0, st>>>(p);
+  } else {
+    if (fy)
+      k_lttb_hull<true, float><<<grid, block, 0, st>>>(p);
+    else
+      k_lttb_hull<true, double><<<grid, block, 0, st>>>(p);
+  }
   return hipGetLastError();
 }
 
