@@ -22,6 +22,7 @@
 #include "common.hpp"
 #include "internal.hpp"
 #include "scan_core.hpp"
+#include "select_core.hpp"
 
 namespace tsds {
 
@@ -290,18 +291,7 @@ __global__ __launch_bounds__(256) void k_batch_compact(BatchArgs a) {
   const int64_t *sel = (const int64_t *)(a.ws + t.o_sel);
   int64_t *dst = mml ? (int64_t *)(a.ws + t.o_cand) + 1 : a.out + t.out_offset;
   const int64_t off_idx = mml ? 1 : 0;
-  const int64_t per = (t.nb + blockDim.x - 1) / blockDim.x;
-  const int64_t b0 = (int64_t)threadIdx.x * per;
-  const int64_t b1 = b0 + per < t.nb ? b0 + per : t.nb;
-  int64_t local = 0;
-  for (int64_t b = b0; b < b1; b++) local += cnt[b];
-  int64_t total;
-  int64_t off = block_exclusive_scan(local, lds, total);
-  for (int64_t b = b0; b < b1; b++) {
-    const int64_t k = cnt[b];
-    for (int64_t j = 0; j < k; j++) dst[off + j] = sel[4 * b + j] + off_idx;
-    off += k;
-  }
+  const int64_t total = compact_bins(cnt, sel, 0, t.nb, dst, 0, off_idx, lds);
   if (threadIdx.x == 0) {
     if (mml) {
       dst[-1] = 0;

@@ -11,6 +11,7 @@
 #include "common.hpp"
 #include "internal.hpp"
 #include "scan_core.hpp"
+#include "select_core.hpp"
 
 namespace tsds {
 
@@ -89,18 +90,7 @@ __device__ void compact_block(const CompactParams &p, int64_t *lds) {
     if (t == 0) *p.out_count = p.all_n;
     return;
   }
-  const int64_t per = (p.nb + blockDim.x - 1) / blockDim.x;
-  const int64_t b0 = (int64_t)t * per;
-  const int64_t b1 = b0 + per < p.nb ? b0 + per : p.nb;
-  int64_t local = 0;
-  for (int64_t b = b0; b < b1; b++) local += p.cnt[b];
-  int64_t total;
-  int64_t off = block_exclusive_scan(local, lds, total);
-  for (int64_t b = b0; b < b1; b++) {
-    const int64_t k = p.cnt[b];
-    for (int64_t j = 0; j < k; j++) out[off + j] = p.sel[4 * b + j] + p.index_offset;
-    off += k;
-  }
+  const int64_t total = compact_bins(p.cnt, p.sel, 0, p.nb, out, 0, p.index_offset, lds);
   if (t == 0) {
     if (p.endpoints_n > 0) {
       out[-1] = 0;
@@ -163,19 +153,9 @@ __global__ __launch_bounds__(1024) void k_compact_offsets(CompactParams p, int64
 
 __global__ __launch_bounds__(256) void k_compact_write(CompactParams p) {
   __shared__ int64_t lds[80];
-  constexpr int64_t per = kCompactBins / 256;
-  const int64_t blk_end = (int64_t)(blockIdx.x + 1) * kCompactBins < p.nb ? (int64_t)(blockIdx.x + 1) * kCompactBins : p.nb;
-  const int64_t b0 = (int64_t)blockIdx.x * kCompactBins + (int64_t)threadIdx.x * per;
-  const int64_t b1 = b0 + per < blk_end ? b0 + per : blk_end;
-  int64_t local = 0;
-  for (int64_t b = b0; b < b1; b++) local += p.cnt[b];
-  int64_t total;
-  int64_t off = block_exclusive_scan(local, lds, total) + p.bsum[blockIdx.x];
-  for (int64_t b = b0; b < b1; b++) {
-    const int64_t k = p.cnt[b];
-    for (int64_t j = 0; j < k; j++) p.out[off + j] = p.sel[4 * b + j] + p.index_offset;
-    off += k;
-  }
+  const int64_t lo = (int64_t)blockIdx.x * kCompactBins;
+  const int64_t hi = lo + kCompactBins < p.nb ? lo + kCompactBins : p.nb;
+  (void)compact_bins(p.cnt, p.sel, lo, hi, p.out, p.bsum[blockIdx.x], p.index_offset, lds);
 }
 
 hipError_t launch_compact(const CompactParams &p, hipStream_t st) {
