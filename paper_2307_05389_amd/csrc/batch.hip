@@ -276,7 +276,7 @@ hipError_t launch_batch_merge(const BatchArgs &a, hipStream_t st) {
 
 // One workgroup per task.  MinMax / M4 write their indices; MinMaxLTTB writes
 // its candidates {0} + (preselection + 1) + {n-1} and their count.
-__global__ __launch_bounds__(256) void k_batch_compact(BatchArgs a) {
+__global__ __launch_bounds__(1024) void k_batch_compact(BatchArgs a) {
   __shared__ int64_t lds[80];
   const BatchTask &t = a.tasks[blockIdx.x];
   const bool mml = t.algo == TS_MINMAXLTTB;
@@ -305,7 +305,7 @@ __global__ __launch_bounds__(256) void k_batch_compact(BatchArgs a) {
 
 hipError_t launch_batch_compact(const BatchArgs &a, hipStream_t st) {
   if (a.ntasks == 0) return hipSuccess;
-  k_batch_compact<<<dim3((unsigned)a.ntasks), dim3(256), 0, st>>>(a);
+  k_batch_compact<<<dim3((unsigned)a.ntasks), dim3(1024), 0, st>>>(a);
   return hipGetLastError();
 }
 

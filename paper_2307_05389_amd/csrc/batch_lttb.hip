@@ -59,7 +59,7 @@ __global__ __launch_bounds__(1024) void k_batch_lttb(BatchArgs a) {
   const bool lds = a.lds_ok && t.m_max <= a.lds_m;
   int32_t *next = p.next, *jump = p.next + p.m_max;
   if (lds) {
-    for (int64_t i = threadIdx.x; i < m - 1; i += blockDim.x) smem[i] = p.next[i];
+    copy_map(p.next, smem, m - 1);
     next = smem;
     jump = smem + a.lds_m;
     __syncthreads();

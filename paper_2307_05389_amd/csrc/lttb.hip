@@ -344,7 +344,7 @@ __global__ __launch_bounds__(1024) void k_lttb_small(LttbParams p, int32_t group
   }
   int32_t *next = p.next, *jump = p.next + p.m_max;
   if (lds_ok) {
-    for (int64_t a = threadIdx.x; a < m - 1; a += blockDim.x) smem[a] = p.next[a];
+    copy_map(p.next, smem, m - 1);
     next = smem;
     jump = smem + p.m_max;
     __syncthreads();

@@ -190,9 +190,34 @@ __device__ inline int32_t lttb_map_one(const LttbParams &p, int64_t m, int64_t a
   return (int32_t)best_in_bucket(p, lo, hi, X_of(p, a), Y_of(p, a), Cx, Cy);
 }
 
+// dst[0 .. cnt) = src[0 .. cnt) by the whole workgroup, in 16-byte pieces
+// with every piece's load issued before any store (one round trip for maps
+// up to 16 pieces per thread).  Both buffers are 16-byte aligned and hold
+// cnt rounded up to a multiple of 4.
+__device__ inline void copy_map(const int32_t *src, int32_t *dst, int64_t cnt) {
+  constexpr int U = 4;
+  const int64_t n4 = (cnt + 3) / 4;
+  const int4 *s4 = (const int4 *)src;
+  int4 *d4 = (int4 *)dst;
+  for (int64_t i0 = threadIdx.x; i0 < n4; i0 += (int64_t)U * blockDim.x) {
+    int4 v[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const int64_t i = i0 + (int64_t)u * blockDim.x;
+      v[u] = s4[i < n4 ? i : n4 - 1];
+    }
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const int64_t i = i0 + (int64_t)u * blockDim.x;
+      if (i < n4) d4[i] = v[u];
+    }
+  }
+}
+
 // LTTB walk over m > n_out points with buckets of a few points, by the whole
 // workgroup, from the transition map next[] (entries 0 .. m-2; see
-// lttb_map_one).  jump[] holds m int32 (LDS or global).
+// lttb_map_one).  jump[] holds m int32 (LDS or global); it takes the group
+// exits, then the picks of the buckets (nb < m).
 __device__ void lttb_walk_map(const LttbParams &p, int64_t m, const int32_t *next, int32_t *jump, int32_t group) {
   const int64_t nb = p.n_out - 2;
   int32_t *entry = p.entry;
@@ -225,15 +250,19 @@ __device__ void lttb_walk_map(const LttbParams &p, int64_t m, const int32_t *nex
   }
   __syncthreads();
 
-  // 3. group interiors in parallel.
+  // 3. group interiors in parallel; the picks go to jump[] (free again), then
+  //    every thread writes outputs, so the index loads behind them are
+  //    independent of the chain.
   for (int64_t g = threadIdx.x; g < G; g += blockDim.x) {
     int32_t v = entry[g];
     const int64_t k1 = (g + 1) * group < nb ? (g + 1) * group : nb;
     for (int64_t k = g * group; k < k1; k++) {
       v = next[v];
-      p.out[k + 1] = src_of(p, v);
+      jump[k] = v;
     }
   }
+  __syncthreads();
+  for (int64_t k = threadIdx.x; k < nb; k += blockDim.x) p.out[k + 1] = src_of(p, jump[k]);
   if (threadIdx.x == 0) {
     p.out[0] = src_of(p, 0);
     p.out[p.n_out - 1] = src_of(p, m - 1);
