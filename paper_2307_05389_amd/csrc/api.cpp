@@ -194,7 +194,7 @@ static LttbMode lttb_mode(bool has_sel, int64_t m_max, int64_t n_out) {
 struct LttbPlan {
   LttbMode mode = kLttbSeq;
   size_t off_cx = 0, off_cy = 0, off_next = 0, off_entry = 0, off_ccnt = 0, off_cidx = 0, off_ccx = 0,
-         off_ccy = 0, off_hnext = 0, off_hjump = 0, off_hflag = 0, bytes = 0;
+         off_ccy = 0, off_hnext = 0, off_hjump = 0, off_hflag = 0, off_gx = 0, off_gy = 0, bytes = 0;
 };
 
 static LttbPlan lttb_plan(int64_t m_max, int64_t n_out, bool has_sel, size_t base) {
@@ -226,6 +226,12 @@ static LttbPlan lttb_plan(int64_t m_max, int64_t n_out, bool has_sel, size_t bas
     o = align256(o + (size_t)lttb_hull_group((int64_t)nb) * kHullCand);
     p.off_hflag = o;
     o = align256(o + sizeof(int32_t));
+  }
+  if (has_sel) {  // the candidates' coordinates, gathered once
+    p.off_gx = o;
+    o = align256(o + sizeof(uint64_t) * (size_t)m_max);
+    p.off_gy = o;
+    o = align256(o + sizeof(uint64_t) * (size_t)m_max);
   }
   p.bytes = o;
   return p;
@@ -433,6 +439,11 @@ static int run_lttb(const ts_series &s, const int64_t *sel, int64_t m, const int
   p.out = out;
   p.out_count = out_count;
   hipError_t e;
+  if (sel) {
+    p.gx = (uint64_t *)wsp(ws, lp.off_gx);
+    p.gy = (uint64_t *)wsp(ws, lp.off_gy);
+    if ((e = launch_lttb_gather(p, st)) != hipSuccess) return hip_fail(e, "lttb candidate gather");
+  }
   if ((e = launch_lttb_centres(p, st)) != hipSuccess) return hip_fail(e, "lttb centres");
   switch (lp.mode) {
     case kLttbSmall: e = launch_lttb_small(p, st); break;

@@ -133,6 +133,12 @@ size_t batch_layout(ts_plan *p, int64_t chunk_bytes) {
       o = al256(o + 8 * (size_t)t.m_max);
       t.o_entry = (int64_t)o;
       o = al256(o + 4 * (lttb_group_count(in.n_out) + 1));
+      if (t.mode == 0) {  // gathered candidate coordinates
+        t.o_gx = (int64_t)o;
+        o = al256(o + 8 * (size_t)t.m_max);
+        t.o_gy = (int64_t)o;
+        o = al256(o + 8 * (size_t)t.m_max);
+      }
       p->max_m = std::max(p->max_m, t.m_max);
     }
     if (in.algo == TS_MINMAXLTTB) p->lttb_tasks.push_back((int32_t)ti);

@@ -27,7 +27,26 @@ __device__ inline LttbParams task_lttb_params(const BatchArgs &a, const BatchTas
   p.entry = (int32_t *)(a.ws + t.o_entry);
   p.out = a.out + t.out_offset;
   p.out_count = a.counts + task;
+  if (t.mode == 0) {
+    p.gx = (uint64_t *)(a.ws + t.o_gx);
+    p.gy = (uint64_t *)(a.ws + t.o_gy);
+  }
   return p;
+}
+
+// The candidates' coordinates of every MinMaxLTTB task with a preselection
+// (blockIdx.x = task, one thread per candidate strided over blockIdx.y).
+__global__ __launch_bounds__(256) void k_batch_lttb_gather(BatchArgs a) {
+  const int64_t task = a.lttb_tasks[blockIdx.x];
+  const BatchTask &t = a.tasks[task];
+  if (t.mode != 0) return;
+  const LttbParams p = task_lttb_params(a, t, task);
+  const int64_t m = points_m(p);
+  for (int64_t j = (int64_t)blockIdx.y * blockDim.x + threadIdx.x; j < m; j += (int64_t)gridDim.y * blockDim.x) {
+    const int64_t s = src_of(p, j);
+    p.gx[j] = coord_word(p.x, p.x_dtype, s);
+    p.gy[j] = coord_word(p.y, p.y_dtype, s);
+  }
 }
 
 // Transition maps of every MinMaxLTTB task: blockIdx.x = task, one thread per
@@ -71,6 +90,7 @@ hipError_t launch_batch_lttb(const BatchArgs &a, hipStream_t st) {
   if (a.n_lttb == 0) return hipSuccess;
   const size_t lds = a.lds_ok ? (size_t)a.lds_m * 2 * sizeof(int32_t) : 0;
   const int64_t ychunks = std::min<int64_t>((a.max_m + 255) / 256, 1024);
+  k_batch_lttb_gather<<<dim3((unsigned)a.n_lttb, (unsigned)std::max<int64_t>(ychunks, 1)), dim3(256), 0, st>>>(a);
   k_batch_lttb_map<<<dim3((unsigned)a.n_lttb, (unsigned)std::max<int64_t>(ychunks, 1)), dim3(256), 0, st>>>(a);
   k_batch_lttb<<<dim3((unsigned)a.n_lttb), dim3(1024), lds, st>>>(a);
   return hipGetLastError();

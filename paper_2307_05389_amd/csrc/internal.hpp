@@ -102,6 +102,12 @@ struct LttbParams {
   int32_t *entry;         // [groups + 1] workspace
   int64_t *out;
   int64_t *out_count;
+  // candidate coordinates gathered after the preselection (NULL: read the
+  // series through sel): one 64-bit word per candidate, the exact integer
+  // (int64, or uint64 bits) for integer dtypes and the index without x, the
+  // double for float dtypes
+  uint64_t *gx;
+  uint64_t *gy;
   // hull-pruned walk of plain LTTB (long buckets); NULL when unused
   int32_t *cand_cnt;      // [nb] candidates of bucket k, 0: walk every point of it
   int64_t *cand_idx;      // [nb * kHullCand]
@@ -120,6 +126,7 @@ constexpr int kHullCand = 64;
 constexpr int kHullLane = 24;
 
 hipError_t launch_lttb_centres(const LttbParams &p, hipStream_t st);
+hipError_t launch_lttb_gather(const LttbParams &p, hipStream_t st);
 hipError_t launch_lttb_hull(const LttbParams &p, hipStream_t st);
 hipError_t launch_lttb_hull_walk(const LttbParams &p, hipStream_t st);
 int64_t lttb_hull_group(int64_t nb);
@@ -146,7 +153,7 @@ struct BatchTask {
   int64_t slot_begin;   // first global bin slot (nb + 1 slots per task)
   int64_t n_out, out_offset;
   int64_t o_edges, o_binres, o_partL, o_partR, o_sel, o_cnt;
-  int64_t o_cand, o_m, o_cx, o_cy, o_next, o_entry;
+  int64_t o_cand, o_m, o_cx, o_cy, o_next, o_entry, o_gx, o_gy;
   const void *yf;       // full series (MinMaxLTTB's LTTB step)
   const void *xf;
   int64_t nf;

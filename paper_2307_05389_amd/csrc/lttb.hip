@@ -321,6 +321,24 @@ hipError_t launch_lttb_centres(const LttbParams &p, hipStream_t st) {
   return hipGetLastError();
 }
 
+// MinMaxLTTB candidates' coordinates as 64-bit words (exact integers, or the
+// doubles the walk uses), one thread per candidate: the centres and the map
+// then read contiguous arrays instead of going through the index list.
+__global__ __launch_bounds__(256) void k_lttb_gather(LttbParams p) {
+  const int64_t m = points_m(p);
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= m) return;
+  const int64_t s = src_of(p, j);
+  p.gx[j] = coord_word(p.x, p.x_dtype, s);
+  p.gy[j] = coord_word(p.y, p.y_dtype, s);
+}
+
+hipError_t launch_lttb_gather(const LttbParams &p, hipStream_t st) {
+  if (p.m_max <= 0) return hipSuccess;
+  k_lttb_gather<<<dim3((unsigned)((p.m_max + 255) / 256)), dim3(256), 0, st>>>(p);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- small
 
 // The transition map of every anchor, one thread each over the whole GPU

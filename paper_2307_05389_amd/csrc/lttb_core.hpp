@@ -64,11 +64,32 @@ __device__ inline double dbl_val(const void *a, int dt, int64_t s) {
   return 0.0;
 }
 
+// Gathered coordinate words (LttbParams::gx / gy): the exact integer for
+// integer dtypes (and the index without x), the double for float dtypes.
+__device__ inline bool float_dt(int dt) { return dt == TS_F16 || dt == TS_F32 || dt == TS_F64; }
+__device__ inline uint64_t coord_word(const void *a, int dt, int64_t s) {
+  if (dt == TS_NONE) return (uint64_t)s;
+  if (float_dt(dt)) return __builtin_bit_cast(uint64_t, dbl_val(a, dt, s));
+  if (dt == TS_U64) return ((const uint64_t *)a)[s];
+  return (uint64_t)(int64_t)int_val(a, dt, s);
+}
+__device__ inline double word_dbl(uint64_t w, int dt) {
+  if (float_dt(dt)) return __builtin_bit_cast(double, w);
+  return dt == TS_U64 ? (double)w : (double)(int64_t)w;
+}
+__device__ inline __int128 word_int(uint64_t w, int dt) {
+  return dt == TS_U64 ? (__int128)w : (__int128)(int64_t)w;
+}
+
 __device__ inline double X_of(const LttbParams &p, int64_t j) {
+  if (p.gx) return word_dbl(p.gx[j], p.x_dtype);
   int64_t s = src_of(p, j);
   return p.x_dtype == TS_NONE ? (double)s : dbl_val(p.x, p.x_dtype, s);
 }
-__device__ inline double Y_of(const LttbParams &p, int64_t j) { return dbl_val(p.y, p.y_dtype, src_of(p, j)); }
+__device__ inline double Y_of(const LttbParams &p, int64_t j) {
+  if (p.gy) return word_dbl(p.gy[j], p.y_dtype);
+  return dbl_val(p.y, p.y_dtype, src_of(p, j));
+}
 
 // Round a 128-bit integer to the nearest double (ties to even).  The top 64
 // significant bits are kept with every discarded bit folded into the lowest
@@ -94,6 +115,18 @@ __device__ inline double i128_to_double(__int128 v) {
 // Mean of X (which == 0) or Y over points [lo, hi), in index order.
 __device__ double coord_mean(const LttbParams &p, int which, int64_t lo, int64_t hi) {
   const double cnt = (double)(hi - lo);
+  const uint64_t *g = which == 0 ? p.gx : p.gy;
+  if (g) {  // gathered words: the same sums, read from contiguous arrays
+    const int dt = which == 0 ? p.x_dtype : p.y_dtype;
+    if (which == 0 ? int_coord_x(p) : int_coord_y(p)) {
+      __int128 s = 0;
+      for (int64_t j = lo; j < hi; j++) s += word_int(g[j], dt);
+      return i128_to_double(s) / cnt;
+    }
+    double s = 0.0;
+    for (int64_t j = lo; j < hi; j++) s += __builtin_bit_cast(double, g[j]);
+    return s / cnt;
+  }
   if (which == 0 && p.x_dtype == TS_NONE) {
     __int128 s = 0;
     for (int64_t j = lo; j < hi; j++) s += src_of(p, j);
