@@ -65,8 +65,8 @@ struct CompactParams {
 
 // Bins per workgroup of the multi-workgroup compaction, and the bin count
 // from which it is used (below it one workgroup scans every bin).
-constexpr int64_t kCompactBins = 4096;
-constexpr int64_t kCompactSingleMax = 65536;
+constexpr int64_t kCompactBins = 1024;
+constexpr int64_t kCompactSingleMax = 4096;
 inline int64_t compact_blocks(int64_t nb) { return (nb + kCompactBins - 1) / kCompactBins; }
 
 size_t elem_size(int dtype);

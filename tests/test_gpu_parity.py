@@ -199,14 +199,16 @@ def test_staged_lanes_per_bin(ts, oracle_mod, dtype):
 
 @pytest.mark.parametrize("dtype", [np.float32, np.uint8, np.int64, np.float16])
 def test_many_bins_compaction(ts, oracle_mod, dtype):
-    """Above 65,536 bins the compaction runs over many workgroups (block sums,
-    their scan, then the writes); n <= n_out fills 0..n-1 from many
-    workgroups."""
+    """Above 4,096 bins the compaction runs over many workgroups (block sums,
+    their scan, then the writes), 1,024 bins per workgroup; n <= n_out fills
+    0..n-1 from many workgroups.  Bin counts around both limits."""
     n = 1_000_003
     y = S.walk(n, dtype, seed=51)
     x = S.timestamps(n, 40, seed=52)
     for xx in (None, x):
-        for algo, n_out in (("minmax", 300_000), ("m4", 400_000), ("minmax", 131_074), ("m4", 1_600_000)):
+        for algo, n_out in (("minmax", 300_000), ("m4", 400_000), ("minmax", 131_074), ("m4", 1_600_000),
+                            ("minmax", 8192), ("minmax", 8194), ("m4", 16392), ("minmax", 2 * 5121),
+                            ("m4", 4 * 1023)):
             say(f"[many bins] {np.dtype(dtype).name} x={xx is not None} {algo} {n_out}")
             assert np.array_equal(gpu(ts, algo, y, n_out, xx), orc(oracle_mod, algo, y, n_out, xx))
         say(f"[many bins] {np.dtype(dtype).name} x={xx is not None} minmaxlttb 40000")
