@@ -281,8 +281,9 @@ void ts_server_free(ts_server *server);
  * of two >= 4096; -1 = automatic) is the slice of y one wavefront reduces;
  * bin segments shorter than small_bin elements (-1 = default 128) are reduced
  * one bin per lane instead of one bin per wavefront; scan_variant (-1 =
- * default, 0..3) picks the tile shape (16-byte vectors per lane per tile and
- * tiles in flight: 0 = 4x2, 1 = 4x1, 2 = 8x1, 3 = 2x2); stage (-1 = automatic:
+ * default, 0..4) picks the tile shape (16-byte vectors per lane per tile and
+ * tiles in flight: 0 = 4x2, 1 = 4x1, 2 = 8x1, 3 = 2x2; 4 = each chunk's
+ * tiles walked once in order, every tile folded into the bins it overlaps); stage (-1 = automatic:
  * on when bins average < 4096 elements, 0 = off, 1 = on) copies each chunk to
  * LDS first and reduces its bins from there (chunk_bytes <= 32768 when on);
  * xclass (-1 = automatic: on for int64 x when bins average at least two
@@ -296,7 +297,7 @@ int ts_set_tuning(int64_t chunk_bytes, int32_t small_bin, int32_t scan_variant, 
 
 /* Host-side query: the scan's tile variant, chunk size (bytes) and kind
  * (0 = chunks with an edge array or closed-form bins, 1 = LDS-staged,
- * 2 = classified from int64 x) for n elements of y_dtype in nb bins, x of
+ * 2 = classified from int64 x, 3 = chunks streamed tile by tile over their bins) for n elements of y_dtype in nb bins, x of
  * x_dtype (TS_NONE: no x), under the current tuning. */
 int ts_scan_config(int y_dtype, int x_dtype, int64_t n, int64_t nb, int32_t *variant, int64_t *chunk_bytes,
                    int32_t *kind);

@@ -85,7 +85,7 @@ CTYPE_NAME = {0: "signed char", 1: "short", 2: "int", 3: "long", 4: "unsigned ch
               6: "unsigned int", 7: "unsigned long", 8: "tsds::half_t", 9: "float", 10: "double"}
 
 
-SCAN_KINDS = {0: "k_scan", 1: "k_scan_staged", 2: "k_scan_xc"}
+SCAN_KINDS = {0: "k_scan", 1: "k_scan_staged", 2: "k_scan_xc", 3: "k_scan_stream"}
 
 
 def scan_config(dtype, n, nb=1, x_dtype=None):
@@ -98,6 +98,10 @@ def scan_config(dtype, n, nb=1, x_dtype=None):
     ct = CTYPE_NAME[DTYPE_CODES[dtype]]
     if k.value == 1:
         return v.value, c.value, f"tsds::k_scan_staged<{ct}>"
+    if k.value == 3:
+        es = torch.empty((), dtype=dtype).element_size()
+        u = 8 if es >= 4 else 4 if es == 2 else 2
+        return v.value, c.value, f"tsds::k_scan_stream<{ct}, {u}>"
     u, nbuf = VARIANT_SHAPE[v.value]
     return v.value, c.value, f"tsds::{SCAN_KINDS[k.value]}<{ct}, {u}, {nbuf}>"
 

@@ -85,6 +85,9 @@ static int32_t g_xclass_override = -1;
 // Bins averaging fewer than kStageBin elements go through LDS-staged chunks
 // of kStageChunk bytes (one HBM round trip per chunk instead of one per bin).
 static const int64_t kStageBin = 4096, kStageChunk = 8192;
+// Streamed chunks: chunk bytes, and the bin size (bytes) from which the
+// per-bin segments of the default shape take over again.
+static const int64_t kStreamChunk = 65536, kStreamMaxBin = 131072;
 
 // Shapes of the scan that classifies chunks from int64 x (sweeps on MI355X
 // over 1e8-point series): its per-chunk set-up costs more than the edge
@@ -121,6 +124,20 @@ static ScanShape scan_shape(int ydt, int xdt, int64_t n, int64_t nb) {
   ScanShape sh = default_shape(ydt);
   if (g_variant_override >= 0) sh.variant = g_variant_override;
   sh.stage = stage;
+  // Bins of a few chunks or less (2- to 8-byte types): the streamed variant
+  // with long chunks walks each chunk's tiles once whatever the bins
+  // (sweeps over 1 GB series on MI355X: 10-25% faster than the per-bin
+  // segments from 8 KB bins up to kStreamMaxBin, and for 2-byte types from
+  // 4 KB bins, where the LDS-staged path took them; bytes stay on the
+  // default shape).
+  const int64_t es = (int64_t)elem_size(ydt), bin_bytes = nb > 0 ? n / nb * es : 0;
+  if (g_variant_override < 0 && g_stage_override != 1 && es >= 2 && bin_bytes < kStreamMaxBin &&
+      bin_bytes >= (es == 2 ? 4096 : 8192)) {
+    sh.variant = kScanStreamVariant;
+    sh.stage = 0;
+    sh.chunk_bytes = g_chunk_bytes_override > 0 ? g_chunk_bytes_override : fit_chunk(kStreamChunk, total, 4096);
+    return sh;
+  }
   if (g_chunk_bytes_override > 0) {
     sh.chunk_bytes = g_chunk_bytes_override;
   } else if (sh.stage) {
@@ -645,7 +662,7 @@ int ts_window(const ts_series *s, int64_t xa, int64_t xb, int64_t *range, void *
 int ts_set_tuning(int64_t chunk_bytes, int32_t small_bin, int32_t scan_variant, int32_t stage, int32_t xclass) {
   if (chunk_bytes > 0 && (chunk_bytes < 4096 || (chunk_bytes & (chunk_bytes - 1))))
     return fail(TS_ERR_ARG, "chunk_bytes must be a power of two >= 4096");
-  if (scan_variant > 3) return fail(TS_ERR_ARG, "scan_variant must be -1..3");
+  if (scan_variant > kScanStreamVariant) return fail(TS_ERR_ARG, "scan_variant must be -1..4");
   if (stage > 1) return fail(TS_ERR_ARG, "stage must be -1, 0 or 1");
   if (xclass > 1) return fail(TS_ERR_ARG, "xclass must be -1, 0 or 1");
   g_chunk_bytes_override = chunk_bytes;
@@ -665,7 +682,7 @@ int ts_scan_config(int y_dtype, int x_dtype, int64_t n, int64_t nb, int32_t *var
   const ScanShape sh = scan_shape(y_dtype, x_dtype, n, nb);
   *variant = sh.variant;
   *chunk_bytes = sh.chunk_bytes;
-  *kind = sh.stage ? 1 : sh.xclass ? 2 : 0;
+  *kind = sh.stage ? 1 : sh.xclass ? 2 : sh.variant == kScanStreamVariant ? 3 : 0;
   return TS_OK;
 }
 

@@ -26,12 +26,16 @@ struct ScanParams {
   Partial *partL;         // [nchunks] bin that started before the chunk
   Partial *partR;         // [nchunks] bin that continues after the chunk
   int32_t small;          // segments shorter than this: one lane per bin
-  int32_t variant;        // tile shape (see launch_scan)
+  int32_t variant;        // tile shape (see launch_scan); kScanStreamVariant: tiles streamed over the chunk's bins
   int32_t stage;          // 1: chunks go through LDS (many small bins per chunk)
   const void *x;          // int64 x when the chunks are classified from x (xclass), else NULL
   int64_t *xedges;        // edge array the x-classified scan writes (nb + 1 entries)
   int32_t xclass;
 };
+
+// Scan variant that walks each chunk's tiles once, in order, folding every
+// tile into the bin segments it overlaps (bins of a few kilobytes).
+constexpr int32_t kScanStreamVariant = 4;
 
 struct MergeParams {
   int64_t n;

@@ -91,6 +91,10 @@ static hipError_t scan_t(const ScanParams &p, hipStream_t st, hipEvent_t e0, hip
     return hipGetLastError();
   }
   void (*k)(ScanParams);
+  if (p.variant == kScanStreamVariant && !p.xclass) {
+    launch_k(k_scan_stream<T, sizeof(T) >= 4 ? 8 : sizeof(T) == 2 ? 4 : 2>, grid, block, 0, st, e0, e1, p);
+    return hipGetLastError();
+  }
   if (p.xclass) {
     switch (p.variant) {
       case 0: k = k_scan_xc<T, 4, 2>; break;

@@ -545,6 +545,98 @@ __device__ void scan_chunk(const ScanParams &p, int64_t c, int lane) {
   }
 }
 
+// ---- chunks streamed tile by tile (bins of a few kilobytes) -----------------
+
+// Largest chunk of the streamed variant (its tile grid starts at the chunk).
+constexpr int64_t kStreamChunkBytes = 65536;
+
+// The same reduction as scan_chunk, for chunks that hold several bins: the
+// chunk's tiles are walked once, in order, on the chunk's own grid, with the
+// next tile in flight while the current one is folded; each bin segment folds
+// the tiles it overlaps (masked at its ends), and a segment that starts in
+// the previous segment's last tile folds that tile again from registers.  So
+// a bin boundary costs a fold, not a fresh round trip to memory.
+template <typename T, int U>
+__device__ void scan_chunk_stream(const ScanParams &p, int64_t c, int lane) {
+  using E = Elem<T>;
+  using C = typename E::C;
+  constexpr int VEC = 16 / (int)sizeof(T);
+  constexpr int64_t TV = (int64_t)kWave * U;
+  const T *__restrict__ y = (const T *)p.y;
+  const u32x4 *__restrict__ base = (const u32x4 *)(y - p.shift);
+  int64_t c0 = c * p.chunk - p.shift;
+  if (c0 < 0) c0 = 0;
+  int64_t c1 = (c + 1) * p.chunk - p.shift;
+  if (c1 > p.n) c1 = p.n;
+  if (p.edges) {
+    const int64_t e0 = p.edges[0], en = p.edges[p.nb];
+    if (c0 < e0) c0 = e0;
+    if (c1 > en) c1 = en;
+  }
+  if (c0 >= c1) return;
+  const int64_t vc0 = (c0 + p.shift) / VEC, vc1 = (c1 + p.shift + VEC - 1) / VEC;
+  const int64_t ntiles = (vc1 - vc0 + TV - 1) / TV;
+  // cur holds tile tc (vectors vc0 + tc*TV ...), nxt tile tc + 1 (in flight)
+  u32x4 cur[U], nxt[U];
+  int64_t tc = 0;
+  load_tile<U>(base, vc0, vc0, vc1, lane, cur);
+  if (ntiles > 1) load_tile<U>(base, vc0 + TV, vc0, vc1, lane, nxt);
+  auto advance = [&]() {
+#pragma unroll
+    for (int u = 0; u < U; u++) cur[u] = nxt[u];
+    tc++;
+    if (tc + 1 < ntiles) load_tile<U>(base, vc0 + (tc + 1) * TV, vc0, vc1, lane, nxt);
+  };
+
+  const CeilMulDiv cm = closed_bins(p.n, p.nb);
+  int64_t b = uniform(first_bin(p.edges, cm, p.n, p.nb, c0, lane));
+  for (;;) {
+    const int64_t bb = b + lane;
+    const bool inb = bb < p.nb;
+    const int64_t s = edge_at(p.edges, cm, p.n, p.nb, bb);
+    const int64_t e = edge_at(p.edges, cm, p.n, p.nb, bb + 1);
+    const int64_t lo = s > c0 ? s : c0;
+    const int64_t hi = e < c1 ? e : c1;
+    const bool valid = inb && lo < hi;
+    const bool before = s < c0, after = e > c1;
+    const bool small = valid && (hi - lo) < p.small;
+    if (small) {
+      C vmn = E::load(y + lo), vmx = vmn;
+      int64_t imn = lo, imx = lo;
+      for (int64_t i = lo + 1; i < hi; i++) {
+        C v = E::load(y + i);
+        if (v < vmn) { vmn = v; imn = i; }
+        if (vmx < v) { vmx = v; imx = i; }
+      }
+      write_result<T>(p, c, bb, before, after, vmn, imn, vmx, imx);
+    }
+    uint64_t big = ballot(valid && !small);
+    while (big) {
+      const int k = __builtin_ctzll(big);
+      big &= big - 1;
+      const int64_t slo = readlane(lo, k), shi = readlane(hi, k);
+      // segments come in index order, so the tiles only move forward
+      const int64_t t_first = ((slo + p.shift) / VEC - vc0) / TV;
+      const int64_t t_last = ((shi - 1 + p.shift) / VEC - vc0) / TV;
+#pragma nounroll
+      while (tc < t_first) advance();
+      SegState<C> st;
+      st.has = false;
+#pragma nounroll
+      for (;;) {
+        fold_tile<T, U>(cur, vc0 + tc * TV, p.shift, slo, shi, lane, st);
+        if (tc >= t_last) break;
+        advance();
+      }
+      const bool sb = readlane(s, k) < c0, sa = readlane(e, k) > c1;
+      if (lane == 0) write_result<T>(p, c, b + k, sb, sa, st.vmn, st.imn, st.vmx, st.imx);
+    }
+    const int64_t e63 = readlane(e, 63);
+    if (e63 >= c1 || b + kWave >= p.nb) break;
+    b += kWave;
+  }
+}
+
 // ---- chunks classified from x (large bins) ----------------------------------
 //
 // Instead of looking its bins up in an edge array, the wavefront reads x at
@@ -936,6 +1028,13 @@ __global__ __launch_bounds__(256) void k_scan(ScanParams p) {
   const int64_t c = uniform((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6));
   if (c >= p.nchunks) return;
   scan_chunk<T, U, NB>(p, c, lane_id());
+}
+
+template <typename T, int U>
+__global__ __launch_bounds__(256) void k_scan_stream(ScanParams p) {
+  const int64_t c = uniform((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6));
+  if (c >= p.nchunks) return;
+  scan_chunk_stream<T, U>(p, c, lane_id());
 }
 
 

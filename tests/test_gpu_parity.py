@@ -136,6 +136,40 @@ def test_tuning_does_not_change_results(ts, oracle_mod, chunk, small, stage, xcl
         ts.set_tuning()
 
 
+@pytest.mark.parametrize("dtype", [np.uint8, np.int8, np.int16, np.float16, np.uint32, np.float32, np.float64,
+                                   np.int64, np.uint64])
+def test_streamed_chunks(ts, oracle_mod, dtype):
+    """The scan variant that walks each chunk's tiles once, in order, and
+    folds every tile into the bin segments it overlaps: bins of one element
+    to several chunks, chunks of 4, 16 and 64 KB and the default, the one-lane
+    threshold on and off, with and without x, series starting off the
+    16-byte grid."""
+    n = 200_003
+    y = S.walk(n, dtype, seed=71)
+    x = S.timestamps(n, 30, seed=72)
+    try:
+        for chunk in (-1, 4096, 16384, 65536):
+            for small in (-1, 1):
+                ts.set_tuning(chunk, small, 4, 0, 0)
+                for off in (0, 3):
+                    yd = dev(y)[off:]
+                    for xx in (None, x[off:]):
+                        xd = None if xx is None else dev(xx)
+                        for algo, n_out in (("minmax", 2), ("minmax", 40), ("minmax", 2000), ("m4", 400),
+                                            ("m4", 40000), ("minmax", 200000), ("minmaxlttb", 1000)):
+                            say(f"[stream] {np.dtype(dtype).name} chunk={chunk} small={small} off={off} "
+                                f"x={xx is not None} {algo} {n_out}")
+                            if algo == "minmaxlttb":
+                                got = ts.minmaxlttb(yd, n_out, x=xd, minmax_ratio=4)
+                            else:
+                                got = getattr(ts, algo)(yd, n_out, x=xd)
+                            torch.cuda.synchronize()
+                            want = orc(oracle_mod, algo, y[off:], n_out, xx)
+                            assert np.array_equal(got.cpu().numpy(), want), (algo, n_out, chunk, small, off)
+    finally:
+        ts.set_tuning()
+
+
 def x_patterns(n, seed):
     """int64 x layouts that stress finding bins from x: steady timestamps,
     long gaps (runs of empty bins, some spanning many chunks), runs of equal
