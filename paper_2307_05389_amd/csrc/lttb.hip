@@ -940,9 +940,13 @@ int64_t lttb_hull_group(int64_t nb) {
 // The walk along the maps, by one workgroup, when every bucket has hull
 // candidates: the exit of each group of S buckets for each entry anchor (in
 // parallel), the chain over the groups, then each group's picks (in
-// parallel): about 3S + nb/S dependent steps instead of nb.  Sets hflag when
-// it has written the result; otherwise k_lttb_hull_walk does the walk.
-__global__ __launch_bounds__(1024) void k_lttb_hull_chase(LttbParams p, int64_t S) {
+// parallel): about 3S + nb/S dependent steps instead of nb.  When the maps
+// fit (lds), next[] is first copied to LDS in one round trip, so every
+// dependent step is an LDS read, and the picks are recorded there and written
+// out by all threads afterwards.  Sets hflag when it has written the result;
+// otherwise k_lttb_hull_walk does the walk.
+__global__ __launch_bounds__(1024) void k_lttb_hull_chase(LttbParams p, int64_t S, int lds) {
+  extern __shared__ uint4 chase_lds[];
   __shared__ int bad;
   __shared__ uint8_t entry_s[4096];
   const int t = threadIdx.x;
@@ -958,6 +962,29 @@ __global__ __launch_bounds__(1024) void k_lttb_hull_chase(LttbParams p, int64_t 
     if (t == 0) *p.hflag = 0;
     return;
   }
+  const uint8_t *hn = p.hnext;
+  uint8_t *hj = p.hjump, *pick = nullptr;
+  if (lds) {  // layout: next [nb * kHullCand], jumps [G * kHullCand], picks [nb]
+    const int64_t n16 = nb * kHullCand / 16;  // kHullCand is a multiple of 16
+    const uint4 *src = (const uint4 *)p.hnext;
+    for (int64_t i0 = t; i0 < n16; i0 += 8 * (int64_t)blockDim.x) {
+      uint4 v[8];
+#pragma unroll
+      for (int u = 0; u < 8; u++) {
+        const int64_t i = i0 + (int64_t)u * blockDim.x;
+        v[u] = src[i < n16 ? i : n16 - 1];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; u++) {
+        const int64_t i = i0 + (int64_t)u * blockDim.x;
+        if (i < n16) chase_lds[i] = v[u];
+      }
+    }
+    hn = (const uint8_t *)chase_lds;
+    hj = (uint8_t *)chase_lds + nb * kHullCand;
+    pick = hj + G * kHullCand;
+    __syncthreads();
+  }
   // 1. group exits
   for (int64_t idx = t; idx < G * kHullCand; idx += blockDim.x) {
     const int64_t g = idx / kHullCand, e = idx % kHullCand;
@@ -965,8 +992,8 @@ __global__ __launch_bounds__(1024) void k_lttb_hull_chase(LttbParams p, int64_t 
     if (e >= ne) continue;
     const int64_t k1 = (g + 1) * S < nb ? (g + 1) * S : nb;
     int v = (int)e;
-    for (int64_t k = g * S; k < k1; k++) v = p.hnext[k * kHullCand + v];
-    p.hjump[g * kHullCand + e] = (uint8_t)v;
+    for (int64_t k = g * S; k < k1; k++) v = hn[k * kHullCand + v];
+    hj[g * kHullCand + e] = (uint8_t)v;
   }
   __threadfence_block();
   __syncthreads();
@@ -975,7 +1002,7 @@ __global__ __launch_bounds__(1024) void k_lttb_hull_chase(LttbParams p, int64_t 
     int v = 0;
     for (int64_t g = 0; g < G; g++) {
       entry_s[g] = (uint8_t)v;
-      v = p.hjump[g * kHullCand + v];
+      v = hj[g * kHullCand + v];
     }
   }
   __syncthreads();
@@ -984,9 +1011,16 @@ __global__ __launch_bounds__(1024) void k_lttb_hull_chase(LttbParams p, int64_t 
     int v = entry_s[g];
     const int64_t k1 = (g + 1) * S < nb ? (g + 1) * S : nb;
     for (int64_t k = g * S; k < k1; k++) {
-      v = p.hnext[k * kHullCand + v];
-      p.out[k + 1] = p.cand_idx[k * kHullCand + v];
+      v = hn[k * kHullCand + v];
+      if (lds)
+        pick[k] = (uint8_t)v;
+      else
+        p.out[k + 1] = p.cand_idx[k * kHullCand + v];
     }
+  }
+  if (lds) {
+    __syncthreads();
+    for (int64_t k = t; k < nb; k += blockDim.x) p.out[k + 1] = p.cand_idx[k * kHullCand + pick[k]];
   }
   if (t == 0) {
     p.out[0] = 0;
@@ -996,10 +1030,19 @@ __global__ __launch_bounds__(1024) void k_lttb_hull_chase(LttbParams p, int64_t 
   }
 }
 
+// LDS of the chase when the maps fit (0: the maps stay in global memory).
+static size_t chase_lds_bytes(int64_t nb, int64_t S) {
+  const int64_t G = (nb + S - 1) / S;
+  const size_t b = (size_t)(nb * kHullCand + G * kHullCand + nb);
+  return b <= 144 * 1024 ? (b + 15) / 16 * 16 : 0;
+}
+
 hipError_t launch_lttb_hull_walk(const LttbParams &p, hipStream_t st) {
   const int64_t nb = p.n_out - 2;
   k_lttb_hull_next<<<dim3((unsigned)nb), dim3(64), 0, st>>>(p);
-  k_lttb_hull_chase<<<dim3(1), dim3(1024), 0, st>>>(p, lttb_hull_group(nb));
+  const int64_t S = lttb_hull_group(nb);
+  const size_t lds = chase_lds_bytes(nb, S);
+  k_lttb_hull_chase<<<dim3(1), dim3(1024), lds, st>>>(p, S, lds > 0 ? 1 : 0);
   k_lttb_hull_walk<<<dim3(1), dim3(64), 0, st>>>(p);
   return hipGetLastError();
 }
