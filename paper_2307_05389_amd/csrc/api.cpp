@@ -82,6 +82,11 @@ static int32_t g_variant_override = -1;
 static int32_t g_stage_override = -1;
 static int32_t g_xclass_override = -1;
 
+// Series of at most kDirectMaxBytes in at least kDirectMinBins bins of at
+// least kDirectMinBin elements: one wavefront per bin instead of chunks (the
+// call is launch-bound there; two launches instead of three).
+static const int64_t kDirectMaxBytes = 8 << 20, kDirectMinBins = 64, kDirectMinBin = 256;
+
 // Bins averaging fewer than kStageBin elements go through LDS-staged chunks
 // of kStageChunk bytes (one HBM round trip per chunk instead of one per bin).
 static const int64_t kStageBin = 4096, kStageChunk = 8192;
@@ -357,7 +362,11 @@ static int run_scan(const ts_series &s, int64_t nb, int m4, const ScanPlan &pl, 
   sp.x = pl.xclass ? s.x : nullptr;
   sp.xedges = pl.xclass ? ed : nullptr;
   if (pl.xclass) sp.edges = nullptr;
-  if ((e = launch_scan(s.y_dtype, sp, st, g_ev_start, g_ev_stop)) != hipSuccess) return hip_fail(e, "scan");
+  // small series without tuning overrides: one wavefront per bin, no merge
+  const bool direct = !pl.xclass && s.n * (int64_t)elem_size(s.y_dtype) <= kDirectMaxBytes && nb >= kDirectMinBins &&
+                      s.n / nb >= kDirectMinBin && g_chunk_bytes_override < 0 && g_small_override < 0 &&
+                      g_variant_override < 0 && g_stage_override < 0 && !g_ev_start;
+  if (!direct && (e = launch_scan(s.y_dtype, sp, st, g_ev_start, g_ev_stop)) != hipSuccess) return hip_fail(e, "scan");
   MergeParams mp;
   mp.n = s.n;
   mp.shift = sp.shift;
@@ -380,7 +389,11 @@ static int run_scan(const ts_series &s, int64_t nb, int m4, const ScanPlan &pl, 
   cp.endpoints_n = endpoints_n;
   cp.all_n = -1;
   cp.bsum = nb > kCompactSingleMax ? (int64_t *)wsp(ws, pl.off_bsum) : nullptr;
-  if ((e = launch_merge(mp, st)) != hipSuccess) return hip_fail(e, "merge");
+  if (direct) {
+    if ((e = launch_bins_direct(s.y_dtype, sp, mp, st)) != hipSuccess) return hip_fail(e, "bins");
+  } else if ((e = launch_merge(mp, st)) != hipSuccess) {
+    return hip_fail(e, "merge");
+  }
   if ((e = launch_compact(cp, st)) != hipSuccess) return hip_fail(e, "compact");
   return TS_OK;
 }

@@ -83,6 +83,9 @@ hipError_t launch_edges_nox(int64_t n, int64_t nb, int64_t *edges, hipStream_t s
 hipError_t launch_scan(int y_dtype, const ScanParams &p, hipStream_t st, hipEvent_t e0 = nullptr,
                        hipEvent_t e1 = nullptr);
 hipError_t launch_merge(const MergeParams &p, hipStream_t st);
+// Small series: one wavefront per bin, selection written directly (replaces
+// the scan and the merge).
+hipError_t launch_bins_direct(int y_dtype, const ScanParams &sp, const MergeParams &mp, hipStream_t st);
 hipError_t launch_compact(const CompactParams &p, hipStream_t st);
 hipError_t launch_binres_to_outputs(const MergeParams &p, int64_t *imin, int64_t *imax,
                                     hipStream_t st);

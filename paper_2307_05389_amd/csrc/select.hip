@@ -50,6 +50,45 @@ __global__ __launch_bounds__(256) void k_merge_lanes(MergeParams p) {
   p.cnt[bin] = bin_selection(s, e, imn, imx, p.m4, p.sel + 4 * bin);
 }
 
+// Small series: one wavefront per bin reduces the whole bin and writes its
+// selection, so no per-chunk partials and no merge launch are needed.
+template <typename T>
+__global__ __launch_bounds__(256) void k_bins_direct(ScanParams sp, MergeParams mp) {
+  const int64_t bin = uniform((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6));
+  if (bin >= mp.nb) return;
+  const int lane = lane_id();
+  int64_t s, e;
+  bin_range(mp, bin, s, e);
+  if (s >= e) {
+    if (lane == 0) mp.cnt[bin] = 0;
+    return;
+  }
+  const u32x4 *__restrict__ base = (const u32x4 *)((const T *)sp.y - sp.shift);
+  u32x4 buf[2][4];
+  SegState<typename Elem<T>::C> st;
+  wave_segment<T, 4, 2>(base, sp.shift, s, e, lane, buf, 0, st);
+  if (lane == 0) mp.cnt[bin] = bin_selection(s, e, st.imn, st.imx, mp.m4, mp.sel + 4 * bin);
+}
+
+hipError_t launch_bins_direct(int ydt, const ScanParams &sp, const MergeParams &mp, hipStream_t st) {
+  const dim3 grid((unsigned)((mp.nb + 3) / 4)), block(256);
+  switch (ydt) {
+    case TS_I8: k_bins_direct<int8_t><<<grid, block, 0, st>>>(sp, mp); break;
+    case TS_I16: k_bins_direct<int16_t><<<grid, block, 0, st>>>(sp, mp); break;
+    case TS_I32: k_bins_direct<int32_t><<<grid, block, 0, st>>>(sp, mp); break;
+    case TS_I64: k_bins_direct<int64_t><<<grid, block, 0, st>>>(sp, mp); break;
+    case TS_U8: k_bins_direct<uint8_t><<<grid, block, 0, st>>>(sp, mp); break;
+    case TS_U16: k_bins_direct<uint16_t><<<grid, block, 0, st>>>(sp, mp); break;
+    case TS_U32: k_bins_direct<uint32_t><<<grid, block, 0, st>>>(sp, mp); break;
+    case TS_U64: k_bins_direct<uint64_t><<<grid, block, 0, st>>>(sp, mp); break;
+    case TS_F16: k_bins_direct<half_t><<<grid, block, 0, st>>>(sp, mp); break;
+    case TS_F32: k_bins_direct<float><<<grid, block, 0, st>>>(sp, mp); break;
+    case TS_F64: k_bins_direct<double><<<grid, block, 0, st>>>(sp, mp); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_merge(const MergeParams &p, hipStream_t st) {
   if (p.n / p.nb <= kLaneMergeChunks * p.chunk)
     k_merge_lanes<<<dim3((unsigned)((p.nb + 255) / 256)), dim3(256), 0, st>>>(p);
