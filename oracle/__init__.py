@@ -43,10 +43,11 @@ def _load():
         lib.oracle_lttb_area2.argtypes = [ctypes.c_double] * 6
         lib.oracle_lttb_area2.restype = ctypes.c_double
         lib.oracle_window.argtypes = [vp, i32, i64, i64, i64, _I64P, _I64P]
+        lib.oracle_everynth.argtypes = [i64, i64, _I64P, _I64P]
         for f in (lib.oracle_argminmax, lib.oracle_edges_nox, lib.oracle_edges_x, lib.oracle_minmax,
                   lib.oracle_m4, lib.oracle_lttb, lib.oracle_minmaxlttb,
                   lib.oracle_minmaxlttb_candidates, lib.oracle_lttb_centres, lib.oracle_lttb_step,
-                  lib.oracle_window):
+                  lib.oracle_window, lib.oracle_everynth):
             f.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -101,6 +102,14 @@ def _run(fn, y, n_out, x, cap, *extra):
     cnt = ctypes.c_int64()
     rc = fn(xp, xd, yp, yd, len(y), n_out, *extra, _i64(out), ctypes.byref(cnt))
     _check(rc, fn.__name__)
+    return out[: cnt.value].copy()
+
+
+def everynth(n, n_out):
+    """EveryNth over n points: every k-th index, k = ceil(n / n_out)."""
+    out = np.empty(max(min(n, n_out), 1), np.int64)
+    cnt = ctypes.c_int64()
+    _check(_load().oracle_everynth(n, n_out, _i64(out), ctypes.byref(cnt)), "everynth")
     return out[: cnt.value].copy()
 
 

@@ -261,6 +261,22 @@ int oracle_minmax(const void *x, int xdt, const void *y, int ydt, int64_t n,
   return 0;
 }
 
+/* EveryNth (Sec. 1 lists it among the downsamplers; Sec. 4 and Table 1
+ * report its constant time): every k-th index 0, k, 2k, ... below n.  The
+ * paper does not give k; the reading here is the smallest stride whose output
+ * fits n_out, k = ceil(n / n_out), so the count is ceil(n / k) <= n_out.
+ * x plays no part (the points are taken by index).  n <= n_out returns every
+ * index; n_out must be >= 1. */
+int oracle_everynth(int64_t n, int64_t n_out, int64_t *out, int64_t *count) {
+  if (!out || !count || n < 0 || n_out < 1) return -1;
+  if (n <= n_out) { *count = emit_all(n, out); return 0; }
+  int64_t k = n / n_out + (n % n_out != 0);
+  int64_t m = 0;
+  for (int64_t i = 0; i < n; i += k) out[m++] = i;
+  *count = m;
+  return 0;
+}
+
 /* M4 (Jugel et al., cited by the paper): nb = n_out / 4 bins; each non-empty
  * bin contributes its first index, argmin, argmax and last index. */
 int oracle_m4(const void *x, int xdt, const void *y, int ydt, int64_t n,

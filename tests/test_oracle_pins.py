@@ -365,6 +365,35 @@ def test_window_matches_searchsorted(oracle_mod):
         assert i0 == np.searchsorted(x, a, "left") and i1 == np.searchsorted(x, b, "right")
 
 
+# ------------------------------------------------------------ EveryNth
+
+
+def test_everynth_invariants(oracle_mod):
+    """Every-k-th selection: starts at 0, constant stride k, fits n_out, and k
+    is the smallest stride that fits (any smaller stride would overflow)."""
+    for n in list(range(0, 40)) + [97, 1000, 1001, 12345]:
+        for n_out in range(1, 45):
+            got = oracle_mod.everynth(n, n_out)
+            if n <= n_out:
+                assert got.tolist() == list(range(n))
+                continue
+            assert got[0] == 0 and len(got) <= n_out
+            d = np.diff(got)
+            k = int(d[0]) if len(d) else n
+            assert (d == k).all()
+            assert got[-1] + k >= n and got[-1] < n           # nothing beyond the last stride is dropped
+            for s in range(1, k):                             # minimality by brute force
+                assert len(range(0, n, s)) > n_out
+
+
+def test_everynth_hand_values(oracle_mod):
+    assert oracle_mod.everynth(10, 3).tolist() == [0, 4, 8]
+    assert oracle_mod.everynth(10, 5).tolist() == [0, 2, 4, 6, 8]
+    assert oracle_mod.everynth(11, 5).tolist() == [0, 3, 6, 9]
+    assert oracle_mod.everynth(7, 1).tolist() == [0]
+    assert oracle_mod.everynth(0, 4).tolist() == []
+
+
 # ------------------------------------------------------------ golden fixtures
 
 
