@@ -149,6 +149,28 @@ int ts_lttb_centres(const ts_series *s, const int64_t *sel, int64_t m, int64_t n
  * device int64[2] `range` (integer x only). */
 int ts_window(const ts_series *s, int64_t xa, int64_t xb, int64_t *range, void *stream);
 
+/* ---- EveryNth and the gather of selected points ------------------------ */
+
+/* EveryNth (listed among the downsamplers in Sec. 1; Table 1): the indices
+ * 0, k, 2k, ... below n with k = ceil(n / n_out), the smallest stride whose
+ * output fits n_out, so *out_count = ceil(n / k) <= n_out.  Only the index
+ * list is written; x and y are not read (the series gives n and is checked
+ * like every other call).  n <= n_out returns 0..n-1.  n_out >= 1.
+ * out_idx: device int64[min(n, n_out)]; out_count: device int64[1].  No
+ * workspace. */
+int ts_everynth(const ts_series *s, int64_t n_out, int64_t *out_idx, int64_t *out_count, void *stream);
+
+/* The selected points themselves (the indices retrieve the representative
+ * subset that is drawn, Sec. 2.3): for i < min(*count, cap),
+ * y_out[i] = y[idx[i]] and, when x_out is not NULL, x_out[i] = x[idx[i]],
+ * in the series' own element types.  idx, count: device int64 (typically a
+ * downsampler's out_idx / out_count, read on the device, so no host sync is
+ * needed); y_out, x_out: device buffers of cap elements aligned to their
+ * element size.  x_out must be NULL when the series has no x.  An index
+ * outside [0, n) writes nothing at its position.  cap = 0 enqueues nothing. */
+int ts_gather(const ts_series *s, const int64_t *idx, const int64_t *count, int64_t cap, void *x_out,
+              void *y_out, void *stream);
+
 /* ---- Batched mode: many series in one pass ---------------------------- */
 
 /* One task: a series, its algorithm (TS_MINMAX, TS_M4 or TS_MINMAXLTTB),

@@ -69,6 +69,10 @@ def lib():
         L.ts_lttb_centres.restype = ctypes.c_int
         L.ts_window.argtypes = [SP, i64, i64, vp, vp]
         L.ts_window.restype = ctypes.c_int
+        L.ts_everynth.argtypes = [SP, i64, vp, vp, vp]
+        L.ts_everynth.restype = ctypes.c_int
+        L.ts_gather.argtypes = [SP, vp, vp, i64, vp, vp, vp]
+        L.ts_gather.restype = ctypes.c_int
         L.ts_set_tuning.argtypes = [i64, i32, i32, i32, i32]
         L.ts_set_tuning.restype = ctypes.c_int
         L.ts_scan_config.argtypes = [ctypes.c_int, ctypes.c_int, i64, i64, ctypes.POINTER(ctypes.c_int32),

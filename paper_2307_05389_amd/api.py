@@ -62,6 +62,35 @@ def minmaxlttb(y, n_out, x=None, minmax_ratio=4):
     return _run("minmaxlttb", y, n_out, x, minmax_ratio)
 
 
+def everynth(y, n_out, x=None):
+    """EveryNth: indices 0, k, 2k, ... below len(y), k = ceil(len(y) / n_out)."""
+    s = L.series(y, x)
+    out = torch.empty(max(min(n_out, y.numel()), 1), dtype=torch.int64, device=y.device)
+    count = torch.zeros(1, dtype=torch.int64, device=y.device)
+    L.check(L.lib().ts_everynth(ctypes.byref(s), n_out, L._ptr(out), L._ptr(count),
+                                L.stream_ptr(device=y.device)))
+    return out[: int(count.item())]
+
+
+def gather(y, idx, x=None, count=None):
+    """The selected points: y[idx] (and x[idx] when x is given), gathered in
+    one kernel.  idx: device int64; count: optional device int64[1] giving
+    how many of idx to take (read on the device).  Returns y_sel, or
+    (x_sel, y_sel) when x is given."""
+    s = L.series(y, x)
+    if idx.dtype != torch.int64 or idx.device != y.device or idx.dim() != 1 or not idx.is_contiguous():
+        raise ValueError("idx must be a contiguous 1-D int64 tensor on y's device")
+    cap = idx.numel()
+    if count is None:
+        count = torch.full((1,), cap, dtype=torch.int64, device=y.device)
+    ys = torch.empty(cap, dtype=y.dtype, device=y.device)
+    xs = torch.empty(cap, dtype=x.dtype, device=y.device) if x is not None else None
+    if cap:
+        L.check(L.lib().ts_gather(ctypes.byref(s), L._ptr(idx), L._ptr(count), cap, L._ptr(xs), L._ptr(ys),
+                                  L.stream_ptr(device=y.device)))
+    return ys if x is None else (xs, ys)
+
+
 def bin_edges(y, nb, x=None):
     """Bin starts edges[0..nb] (edges[nb] = n) used by MinMax / M4."""
     s = L.series(y, x)

@@ -671,6 +671,36 @@ int ts_window(const ts_series *s, int64_t xa, int64_t xb, int64_t *range, void *
   return TS_OK;
 }
 
+int ts_everynth(const ts_series *s, int64_t n_out, int64_t *out_idx, int64_t *out_count, void *stream) {
+  int rc;
+  if ((rc = check_series(s))) return rc;
+  if (n_out < 1) return fail(TS_ERR_ARG, "EveryNth needs n_out >= 1 (got %lld)", (long long)n_out);
+  if (!out_idx || !out_count) return fail(TS_ERR_NULL, "out_idx / out_count is NULL");
+  const int64_t n = s->n;
+  const int64_t k = n <= n_out ? 1 : n / n_out + (n % n_out != 0);
+  const int64_t m = n <= n_out ? n : (n + k - 1) / k;
+  hipError_t e = launch_everynth(k, m, out_idx, out_count, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "everynth");
+  return TS_OK;
+}
+
+int ts_gather(const ts_series *s, const int64_t *idx, const int64_t *count, int64_t cap, void *x_out,
+              void *y_out, void *stream) {
+  int rc;
+  if ((rc = check_series(s))) return rc;
+  if (cap < 0) return fail(TS_ERR_ARG, "cap = %lld < 0", (long long)cap);
+  if (cap == 0) return TS_OK;
+  if (!idx || !count || !y_out) return fail(TS_ERR_NULL, "idx / count / y_out is NULL");
+  if (x_out && !s->x) return fail(TS_ERR_NULL, "x_out given for a series without x");
+  const int ys = (int)elem_size(s->y_dtype), xs = s->x ? (int)elem_size(s->x_dtype) : 0;
+  if ((uintptr_t)y_out % ys) return fail(TS_ERR_ALIGN, "y_out is not aligned to y's element size");
+  if (x_out && ((uintptr_t)x_out % xs)) return fail(TS_ERR_ALIGN, "x_out is not aligned to x's element size");
+  if (((uintptr_t)idx | (uintptr_t)count) % 8) return fail(TS_ERR_ALIGN, "idx / count is not 8-byte aligned");
+  hipError_t e = launch_gather(s->x, xs, s->y, ys, s->n, idx, count, cap, x_out, y_out, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "gather");
+  return TS_OK;
+}
+
 // Tuning knobs (tests use them to show that results do not depend on them).
 int ts_set_tuning(int64_t chunk_bytes, int32_t small_bin, int32_t scan_variant, int32_t stage, int32_t xclass) {
   if (chunk_bytes > 0 && (chunk_bytes < 4096 || (chunk_bytes & (chunk_bytes - 1))))

@@ -228,4 +228,11 @@ hipError_t launch_copy_bytes(void *dst, const void *src, size_t bytes, hipStream
 hipError_t launch_export_rows(const int64_t *counts, const int64_t *rows, int64_t row, int n, int64_t *h_counts,
                               int64_t *h_rows, hipStream_t st);
 
+// EveryNth: out[i] = i*k for i < m, *count = m.
+hipError_t launch_everynth(int64_t k, int64_t m, int64_t *out, int64_t *count, hipStream_t st);
+// Gather of selected points, moved as raw words: xs, ys are the element sizes
+// (xs = 0 or xo = NULL: y only).  Indices outside [0, n) are skipped.
+hipError_t launch_gather(const void *x, int xs, const void *y, int ys, int64_t n, const int64_t *idx,
+                         const int64_t *count, int64_t cap, void *xo, void *yo, hipStream_t st);
+
 }  // namespace tsds
