@@ -33,7 +33,8 @@ def _load():
         lib.oracle_argminmax.argtypes = [vp, i32, i64, i64, _I64P, _I64P]
         lib.oracle_edges_nox.argtypes = [i64, i64, _I64P]
         lib.oracle_edges_x.argtypes = [vp, i32, i64, i64, _I64P]
-        for f in (lib.oracle_minmax, lib.oracle_m4, lib.oracle_lttb):
+        lib.oracle_nan_argminmax.argtypes = [vp, i32, i64, i64, _I64P, _I64P]
+        for f in (lib.oracle_minmax, lib.oracle_m4, lib.oracle_lttb, lib.oracle_nan_minmax, lib.oracle_nan_m4):
             f.argtypes = [vp, i32, vp, i32, i64, i64, _I64P, _I64P]
         lib.oracle_minmaxlttb.argtypes = [vp, i32, vp, i32, i64, i64, i64, _I64P, _I64P]
         lib.oracle_minmaxlttb_candidates.argtypes = [vp, i32, vp, i32, i64, i64, i64, _I64P, _I64P]
@@ -47,7 +48,8 @@ def _load():
         for f in (lib.oracle_argminmax, lib.oracle_edges_nox, lib.oracle_edges_x, lib.oracle_minmax,
                   lib.oracle_m4, lib.oracle_lttb, lib.oracle_minmaxlttb,
                   lib.oracle_minmaxlttb_candidates, lib.oracle_lttb_centres, lib.oracle_lttb_step,
-                  lib.oracle_window, lib.oracle_everynth):
+                  lib.oracle_window, lib.oracle_everynth, lib.oracle_nan_argminmax, lib.oracle_nan_minmax,
+                  lib.oracle_nan_m4):
             f.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -119,6 +121,16 @@ def minmax(y, n_out, x=None):
 
 def m4(y, n_out, x=None):
     return _run(_load().oracle_m4, y, n_out, x, max(n_out, len(y) if len(y) <= n_out else 0))
+
+
+def nan_minmax(y, n_out, x=None):
+    """NaN-aware MinMax: NaN skipped; an all-NaN bin keeps its first index."""
+    return _run(_load().oracle_nan_minmax, y, n_out, x, max(n_out, len(y) if len(y) <= n_out else 0))
+
+
+def nan_m4(y, n_out, x=None):
+    """NaN-aware M4: NaN skipped in the argmin/argmax; first and last kept."""
+    return _run(_load().oracle_nan_m4, y, n_out, x, max(n_out, len(y) if len(y) <= n_out else 0))
 
 
 def lttb(y, n_out, x=None):

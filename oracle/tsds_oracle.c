@@ -304,6 +304,73 @@ int oracle_m4(const void *x, int xdt, const void *y, int ydt, int64_t n,
 }
 
 /* ------------------------------------------------------------------ */
+/* NaN-aware MinMax and M4.  The paper only remarks that floats need a   */
+/* different initial value once NaN is handled (Sec. 2.1, Listing 1);   */
+/* the reading here: NaN values are passed over, and a bin holding only  */
+/* NaN keeps its first index as both argmin and argmax.                  */
+/* ------------------------------------------------------------------ */
+
+static int is_nan(oval v) { return v.cls == CLS_FLOAT && v.f != v.f; }
+
+/* Scan y[lo..hi) in index order; the first non-NaN value starts both running
+ * extremes and later ones replace them only when strictly smaller (larger).
+ * With no non-NaN value both results are lo.  Requires lo < hi. */
+int oracle_nan_argminmax(const void *y, int ydt, int64_t lo, int64_t hi,
+                         int64_t *imin, int64_t *imax) {
+  if (!y || !imin || !imax || !dtype_valid(ydt) || lo < 0 || hi <= lo) return -1;
+  int64_t amin = -1, amax = -1;
+  oval vmin, vmax;
+  for (int64_t i = lo; i < hi; i++) {
+    oval v = load(y, ydt, i);
+    if (is_nan(v)) continue;
+    if (amin < 0 || less(v, vmin)) { vmin = v; amin = i; }
+    if (amax < 0 || greater(v, vmax)) { vmax = v; amax = i; }
+  }
+  *imin = amin < 0 ? lo : amin;
+  *imax = amax < 0 ? lo : amax;
+  return 0;
+}
+
+/* The MinMax (m4 = 0) or M4 (m4 = 1) selection over the same bins as
+ * oracle_minmax / oracle_m4, per bin with oracle_nan_argminmax. */
+static int nan_binned(const void *x, int xdt, const void *y, int ydt, int64_t n,
+                      int64_t n_out, int m4, int64_t *out, int64_t *count) {
+  if (!y || !out || !count || !dtype_valid(ydt) || n < 0) return -1;
+  const int64_t per = m4 ? 4 : 2;
+  if (n_out < per || n_out % per) return -1;
+  if (n <= n_out) { *count = emit_all(n, out); return 0; }
+  int64_t nb = n_out / per;
+  int64_t *edges = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nb + 1));
+  if (!edges) return -3;
+  int rc = make_edges(x, xdt, n, nb, edges);
+  if (rc) { free(edges); return rc; }
+  int64_t m = 0;
+  for (int64_t b = 0; b < nb; b++) {
+    if (edges[b] >= edges[b + 1]) continue;
+    int64_t v[4];
+    int k = 0;
+    if (m4) v[k++] = edges[b];
+    oracle_nan_argminmax(y, ydt, edges[b], edges[b + 1], &v[k], &v[k + 1]);
+    k += 2;
+    if (m4) v[k++] = edges[b + 1] - 1;
+    m += emit_sorted_distinct(v, k, out + m);
+  }
+  free(edges);
+  *count = m;
+  return 0;
+}
+
+int oracle_nan_minmax(const void *x, int xdt, const void *y, int ydt, int64_t n,
+                      int64_t n_out, int64_t *out, int64_t *count) {
+  return nan_binned(x, xdt, y, ydt, n, n_out, 0, out, count);
+}
+
+int oracle_nan_m4(const void *x, int xdt, const void *y, int ydt, int64_t n,
+                  int64_t n_out, int64_t *out, int64_t *count) {
+  return nan_binned(x, xdt, y, ydt, n, n_out, 1, out, count);
+}
+
+/* ------------------------------------------------------------------ */
 /* LTTB (Steinarsson 2013, cited by the paper as the algorithm whose     */
 /* bucket walk cannot be parallelised; Sec. 4).                         */
 /* ------------------------------------------------------------------ */

@@ -49,6 +49,39 @@ def per_bin(y, ids, nb, kind):
     return np.array(out, np.int64)
 
 
+def per_bin_nan(y, ids, nb, kind):
+    """per_bin with NaN ignored: numpy's argmin / argmax over the bin's
+    non-NaN values only (first occurrence), mapped back to their positions
+    (numpy's nanargmin / nanargmax would not do: they stand NaN in for +-inf,
+    so a NaN can tie with an infinity); a bin of NaN only gives its first
+    index for both."""
+    out = []
+    for b in range(nb):
+        idx = np.nonzero(ids == b)[0]
+        if len(idx) == 0:
+            continue
+        seg = y[idx[0]: idx[-1] + 1].astype(np.float64)
+        if np.isnan(seg).all():
+            pick = {int(idx[0])}
+        else:
+            keep = np.nonzero(~np.isnan(seg))[0]
+            vals = seg[keep]
+            pick = {idx[0] + int(keep[np.argmin(vals)]), idx[0] + int(keep[np.argmax(vals)])}
+        if kind == "m4":
+            pick |= {int(idx[0]), int(idx[-1])}
+        out.extend(sorted(pick))
+    return np.array(out, np.int64)
+
+
+def nan_binned(y, n_out, kind, x=None):
+    n = len(y)
+    if n <= n_out:
+        return np.arange(n, dtype=np.int64)
+    nb = n_out // (2 if kind == "minmax" else 4)
+    ids = bin_ids_nox(n, nb) if x is None else bin_ids_int_x(x, nb)
+    return per_bin_nan(y, ids, nb, kind)
+
+
 def minmax(y, n_out, x=None):
     n = len(y)
     if n <= n_out:

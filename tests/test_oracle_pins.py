@@ -394,6 +394,59 @@ def test_everynth_hand_values(oracle_mod):
     assert oracle_mod.everynth(0, 4).tolist() == []
 
 
+# ------------------------------------------------------------ NaN-aware MinMax / M4
+
+
+@pytest.mark.parametrize("alphabet", [
+    np.array([np.nan, 0.0, 1.0]),
+    np.array([np.nan, -np.inf, np.inf]),
+    np.array([-0.0, np.nan, 0.0]),
+])
+@pytest.mark.parametrize("dt", [np.float16, np.float32, np.float64])
+def test_nan_exhaustive_tiny(oracle_mod, alphabet, dt):
+    """Every series of length <= 6 over a NaN-holding alphabet, against
+    numpy's nanargmin / nanargmax per brute-force bin."""
+    alphabet = alphabet.astype(dt)
+    for n in range(0, 7):
+        for combo in itertools.product(range(len(alphabet)), repeat=n):
+            y = alphabet[list(combo)] if n else alphabet[:0]
+            for kind in ("minmax", "m4"):
+                for n_out in _valid_nouts(kind, n):
+                    got = getattr(oracle_mod, "nan_" + kind)(y, n_out)
+                    exp = brute.nan_binned(y, n_out, kind)
+                    assert np.array_equal(got, exp), (kind, y, n_out, got, exp)
+
+
+def test_nan_random_with_x(oracle_mod):
+    rng = np.random.default_rng(31)
+    for trial in range(40):
+        n = int(rng.integers(10, 400))
+        y = rng.normal(size=n)
+        y[rng.random(n) < rng.choice([0.0, 0.2, 0.9, 1.0])] = np.nan
+        x = np.sort(rng.integers(0, 5 * n, n)).astype(np.int64) if trial % 2 else None
+        for kind, n_out in (("minmax", 8), ("minmax", 40), ("m4", 8), ("m4", 40)):
+            got = getattr(oracle_mod, "nan_" + kind)(y, n_out, x=x)
+            assert np.array_equal(got, brute.nan_binned(y, n_out, kind, x=x)), (trial, kind, n_out)
+
+
+@pytest.mark.parametrize("dtype", ALL_DTYPES)
+def test_nan_variants_equal_plain_without_nan(oracle_mod, dtype):
+    """No NaN in y: the NaN-aware selection is the plain one."""
+    y = S.walk(3001, dtype, seed=12)
+    x = S.timestamps(3001, 50, seed=13)
+    for kind, n_out in (("minmax", 100), ("m4", 100)):
+        for xx in (None, x):
+            assert np.array_equal(getattr(oracle_mod, "nan_" + kind)(y, n_out, x=xx),
+                                  getattr(oracle_mod, kind)(y, n_out, x=xx))
+
+
+def test_nan_all_nan_series(oracle_mod):
+    y = np.full(1000, np.nan)
+    edges = [-(-(b * 999) // 50) for b in range(50)] + [1000]
+    assert oracle_mod.nan_minmax(y, 100).tolist() == edges[:50]
+    assert oracle_mod.nan_m4(y, 200).tolist() == sorted(set(edges[:50]) | {e - 1 for e in edges[1:]})
+
+
 # ------------------------------------------------------------ golden fixtures
 
 
