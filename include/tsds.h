@@ -63,7 +63,7 @@ enum {
 };
 
 /* Algorithms. */
-enum { TS_MINMAX = 0, TS_M4 = 1, TS_LTTB = 2, TS_MINMAXLTTB = 3 };
+enum { TS_MINMAX = 0, TS_M4 = 1, TS_LTTB = 2, TS_MINMAXLTTB = 3, TS_NAN_MINMAX = 4, TS_NAN_M4 = 5 };
 
 /* One series.  y: n elements of y_dtype (any of the 11 types).
  * x: NULL (x_dtype = TS_NONE) or n sorted elements of x_dtype in
@@ -123,6 +123,19 @@ int ts_lttb(const ts_series *s, int64_t n_out, int64_t *out_idx, int64_t *out_co
  * original coordinates.  minmax_ratio >= 1, n_out*minmax_ratio even. */
 int ts_minmaxlttb(const ts_series *s, int64_t n_out, int64_t minmax_ratio, int64_t *out_idx,
                   int64_t *out_count, void *ws, size_t ws_bytes, void *stream);
+
+/* NaN-aware MinMax and M4 (the paper flags NaN as needing a different
+ * initial value, Sec. 2.1, Listing 1, and defines no more).  Reading: NaN
+ * values of y are skipped; a bin holding only NaN keeps its first index as
+ * both argmin and argmax (so MinMax returns that one index and M4 its first
+ * and last).  Everything else (bins, ties, +-0, de-duplication, n <= n_out,
+ * n_out rules, workspace via ts_workspace_bytes(TS_NAN_MINMAX / TS_NAN_M4))
+ * is as for ts_minmax / ts_m4, and these are the only calls for which y may
+ * hold NaN.  Integer y holds no NaN: the result equals ts_minmax / ts_m4. */
+int ts_nan_minmax(const ts_series *s, int64_t n_out, int64_t *out_idx, int64_t *out_count,
+                  void *ws, size_t ws_bytes, void *stream);
+int ts_nan_m4(const ts_series *s, int64_t n_out, int64_t *out_idx, int64_t *out_count,
+              void *ws, size_t ws_bytes, void *stream);
 
 /* ---- Single steps of the path, exposed so each can be checked alone ---- */
 

@@ -15,15 +15,18 @@ device and the current stream; see include/tsds.h for the exact semantics.
 """
 from .api import (  # noqa: F401
     bin_argminmax, bin_edges, downsample_into, everynth, gather, lttb, lttb_centres, m4, minmax, minmaxlttb,
+    nan_m4, nan_minmax,
     set_tuning, window, workspace_bytes,
 )
 from .downsamplers import (  # noqa: F401
     EveryNthDownsampler, LTTBDownsampler, M4Downsampler, MinMaxDownsampler, MinMaxLTTBDownsampler,
+    NaNM4Downsampler, NaNMinMaxDownsampler,
 )
 from ._lib import TsArgError, TsError, lib  # noqa: F401
 from .batch import Batch  # noqa: F401
 from .serve import Server  # noqa: F401
 
-__all__ = ["minmax", "m4", "lttb", "minmaxlttb", "everynth", "gather", "MinMaxDownsampler", "M4Downsampler",
+__all__ = ["minmax", "m4", "lttb", "minmaxlttb", "everynth", "gather", "nan_minmax", "nan_m4",
+           "NaNMinMaxDownsampler", "NaNM4Downsampler", "MinMaxDownsampler", "M4Downsampler",
            "LTTBDownsampler", "MinMaxLTTBDownsampler", "EveryNthDownsampler", "downsample_into", "workspace_bytes", "bin_edges",
            "bin_argminmax", "lttb_centres", "window", "set_tuning", "Batch", "Server", "TsError", "TsArgError"]

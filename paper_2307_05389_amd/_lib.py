@@ -18,7 +18,7 @@ DTYPE_CODES = {
     torch.uint8: 4, torch.uint16: 5, torch.uint32: 6, torch.uint64: 7,
     torch.float16: 8, torch.float32: 9, torch.float64: 10,
 }
-ALGO = {"minmax": 0, "m4": 1, "lttb": 2, "minmaxlttb": 3}
+ALGO = {"minmax": 0, "m4": 1, "lttb": 2, "minmaxlttb": 3, "nan_minmax": 4, "nan_m4": 5}
 ERRORS = {-1: "TS_ERR_ARG", -2: "TS_ERR_DTYPE", -3: "TS_ERR_NULL", -4: "TS_ERR_WORKSPACE",
           -5: "TS_ERR_HIP", -6: "TS_ERR_ALIGN"}
 
@@ -54,7 +54,7 @@ def lib():
         L.ts_last_error.restype = ctypes.c_char_p
         L.ts_workspace_bytes.argtypes = [ctypes.c_int, SP, i64, i64]
         L.ts_workspace_bytes.restype = sz
-        for f in (L.ts_minmax, L.ts_m4, L.ts_lttb):
+        for f in (L.ts_minmax, L.ts_m4, L.ts_lttb, L.ts_nan_minmax, L.ts_nan_m4):
             f.argtypes = [SP, i64, vp, vp, vp, sz, vp]
             f.restype = ctypes.c_int
         L.ts_minmaxlttb.argtypes = [SP, i64, i64, vp, vp, vp, sz, vp]

@@ -28,7 +28,8 @@ def downsample_into(algo, y, n_out, out, count, x=None, minmax_ratio=4, workspac
     if algo == "minmaxlttb":
         rc = lib.ts_minmaxlttb(ctypes.byref(s), n_out, minmax_ratio, L._ptr(out), L._ptr(count), wsp, wsb, sp)
     else:
-        f = {"minmax": lib.ts_minmax, "m4": lib.ts_m4, "lttb": lib.ts_lttb}[algo]
+        f = {"minmax": lib.ts_minmax, "m4": lib.ts_m4, "lttb": lib.ts_lttb, "nan_minmax": lib.ts_nan_minmax,
+             "nan_m4": lib.ts_nan_m4}[algo]
         rc = f(ctypes.byref(s), n_out, L._ptr(out), L._ptr(count), wsp, wsb, sp)
     L.check(rc)
     return out, count
@@ -49,6 +50,16 @@ def minmax(y, n_out, x=None):
 def m4(y, n_out, x=None):
     """M4: per bin the first, argmin, argmax and last index (n_out/4 bins)."""
     return _run("m4", y, n_out, x, 0)
+
+
+def nan_minmax(y, n_out, x=None):
+    """NaN-aware MinMax: NaN values skipped; an all-NaN bin keeps its first index."""
+    return _run("nan_minmax", y, n_out, x, 0)
+
+
+def nan_m4(y, n_out, x=None):
+    """NaN-aware M4: NaN values skipped in the argmin/argmax; first and last kept."""
+    return _run("nan_m4", y, n_out, x, 0)
 
 
 def lttb(y, n_out, x=None):

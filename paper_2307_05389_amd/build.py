@@ -16,7 +16,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libtsds.so")
 
-SOURCES = ["scan.hip", "select.hip", "window.hip", "pick.hip", "lttb.hip", "api.cpp", "batch.hip", "batch_lttb.hip", "api_batch.cpp"]
+SOURCES = ["scan.hip", "select.hip", "window.hip", "pick.hip", "nan.hip", "lttb.hip", "api.cpp", "batch.hip", "batch_lttb.hip", "api_batch.cpp"]
 EXTRA_SOURCES = ["serve.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -163,6 +163,7 @@ static int32_t small_threshold() { return g_small_override > 0 ? g_small_overrid
 struct ScanPlan {
   int64_t nb = 0, chunk = 0, nchunks = 0;
   int32_t variant = 0, stage = 0, xclass = 0;
+  bool nan = false;  // NaN-aware scan (floating-point y)
   size_t off_edges = 0, off_binres = 0, off_partL = 0, off_partR = 0, off_sel = 0, off_cnt = 0, off_bsum = 0,
          bytes = 0;
 };
@@ -170,10 +171,23 @@ struct ScanPlan {
 // Workspace of one argmin/argmax pass over n elements in nb bins.  The chunk
 // count allows for the largest possible misalignment of y, so the size does
 // not depend on the pointer.
-static ScanPlan scan_plan(int ydt, int xdt, int64_t n, int64_t nb, size_t base) {
+static bool float_dtype(int dt) { return dt == TS_F16 || dt == TS_F32 || dt == TS_F64; }
+
+// Chunk of the NaN-aware scan.
+static const int64_t kNanChunk = 32768;
+
+static ScanPlan scan_plan(int ydt, int xdt, int64_t n, int64_t nb, size_t base, bool nan = false) {
   ScanPlan p;
   const bool need_edges = xdt != TS_NONE;
-  const ScanShape sh = scan_shape(ydt, xdt, n, nb);
+  ScanShape sh = scan_shape(ydt, xdt, n, nb);
+  p.nan = nan && float_dtype(ydt);
+  if (p.nan) {  // one chunk-major kernel: edges searched first, no staging or streaming
+    sh.variant = 0;
+    sh.stage = 0;
+    sh.xclass = 0;
+    sh.chunk_bytes = g_chunk_bytes_override > 0 ? g_chunk_bytes_override
+                                                : fit_chunk(kNanChunk, n * (int64_t)elem_size(ydt), 4096);
+  }
   p.nb = nb;
   p.chunk = sh.chunk_bytes / (int64_t)elem_size(ydt);
   p.variant = sh.variant;
@@ -302,9 +316,11 @@ static int check_ws(void *ws, size_t ws_bytes, size_t need) {
 
 static int check_nout(int algo, int64_t n_out, int64_t ratio) {
   switch (algo) {
+    case TS_NAN_MINMAX:
     case TS_MINMAX:
       if (n_out < 2 || n_out % 2) return fail(TS_ERR_ARG, "MinMax n_out must be even and >= 2 (got %lld)", (long long)n_out);
       return check_bins(2, n_out / 2);
+    case TS_NAN_M4:
     case TS_M4:
       if (n_out < 4 || n_out % 4) return fail(TS_ERR_ARG, "M4 n_out must be a multiple of 4 (got %lld)", (long long)n_out);
       return check_bins(2, n_out / 4);
@@ -363,10 +379,14 @@ static int run_scan(const ts_series &s, int64_t nb, int m4, const ScanPlan &pl, 
   sp.xedges = pl.xclass ? ed : nullptr;
   if (pl.xclass) sp.edges = nullptr;
   // small series without tuning overrides: one wavefront per bin, no merge
-  const bool direct = !pl.xclass && s.n * (int64_t)elem_size(s.y_dtype) <= kDirectMaxBytes && nb >= kDirectMinBins &&
+  const bool direct = !pl.nan && !pl.xclass && s.n * (int64_t)elem_size(s.y_dtype) <= kDirectMaxBytes && nb >= kDirectMinBins &&
                       s.n / nb >= kDirectMinBin && g_chunk_bytes_override < 0 && g_small_override < 0 &&
                       g_variant_override < 0 && g_stage_override < 0 && !g_ev_start;
-  if (!direct && (e = launch_scan(s.y_dtype, sp, st, g_ev_start, g_ev_stop)) != hipSuccess) return hip_fail(e, "scan");
+  if (pl.nan) {
+    if ((e = launch_scan_nan(s.y_dtype, sp, st)) != hipSuccess) return hip_fail(e, "nan scan");
+  } else if (!direct && (e = launch_scan(s.y_dtype, sp, st, g_ev_start, g_ev_stop)) != hipSuccess) {
+    return hip_fail(e, "scan");
+  }
   MergeParams mp;
   mp.n = s.n;
   mp.shift = sp.shift;
@@ -507,6 +527,8 @@ size_t ts_workspace_bytes(int algo, const ts_series *s, int64_t n_out, int64_t m
   switch (algo) {
     case TS_MINMAX: return scan_plan(s->y_dtype, s->x_dtype, s->n, n_out / 2, 0).bytes;
     case TS_M4: return scan_plan(s->y_dtype, s->x_dtype, s->n, n_out / 4, 0).bytes;
+    case TS_NAN_MINMAX: return scan_plan(s->y_dtype, s->x_dtype, s->n, n_out / 2, 0, true).bytes;
+    case TS_NAN_M4: return scan_plan(s->y_dtype, s->x_dtype, s->n, n_out / 4, 0, true).bytes;
     case TS_LTTB: return lttb_plan(s->n, n_out, false, 0).bytes;
     case TS_MINMAXLTTB: return mml_plan(*s, n_out, minmax_ratio).bytes;
   }
@@ -520,11 +542,12 @@ static int minmax_m4(int algo, const ts_series *s, int64_t n_out, int64_t *out_i
     return rc;
   hipStream_t st = (hipStream_t)stream;
   if (s->n <= n_out) return write_all(s->n, out_idx, out_count, st);
-  const int64_t nb = algo == TS_MINMAX ? n_out / 2 : n_out / 4;
+  const bool m4 = algo == TS_M4 || algo == TS_NAN_M4;
+  const int64_t nb = m4 ? n_out / 4 : n_out / 2;
   if ((rc = check_bins(s->n, nb))) return rc;
-  const ScanPlan pl = scan_plan(s->y_dtype, s->x_dtype, s->n, nb, 0);
+  const ScanPlan pl = scan_plan(s->y_dtype, s->x_dtype, s->n, nb, 0, algo == TS_NAN_MINMAX || algo == TS_NAN_M4);
   if ((rc = check_ws(ws, ws_bytes, pl.bytes))) return rc;
-  return run_scan(*s, nb, algo == TS_M4, pl, ws, out_idx, out_count, 0, 0, st);
+  return run_scan(*s, nb, m4, pl, ws, out_idx, out_count, 0, 0, st);
 }
 
 int ts_minmax(const ts_series *s, int64_t n_out, int64_t *out_idx, int64_t *out_count, void *ws,
@@ -535,6 +558,16 @@ int ts_minmax(const ts_series *s, int64_t n_out, int64_t *out_idx, int64_t *out_
 int ts_m4(const ts_series *s, int64_t n_out, int64_t *out_idx, int64_t *out_count, void *ws, size_t ws_bytes,
           void *stream) {
   return minmax_m4(TS_M4, s, n_out, out_idx, out_count, ws, ws_bytes, stream);
+}
+
+int ts_nan_minmax(const ts_series *s, int64_t n_out, int64_t *out_idx, int64_t *out_count, void *ws,
+                  size_t ws_bytes, void *stream) {
+  return minmax_m4(TS_NAN_MINMAX, s, n_out, out_idx, out_count, ws, ws_bytes, stream);
+}
+
+int ts_nan_m4(const ts_series *s, int64_t n_out, int64_t *out_idx, int64_t *out_count, void *ws, size_t ws_bytes,
+              void *stream) {
+  return minmax_m4(TS_NAN_M4, s, n_out, out_idx, out_count, ws, ws_bytes, stream);
 }
 
 int ts_lttb(const ts_series *s, int64_t n_out, int64_t *out_idx, int64_t *out_count, void *ws, size_t ws_bytes,

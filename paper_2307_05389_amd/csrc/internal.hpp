@@ -228,6 +228,10 @@ hipError_t launch_copy_bytes(void *dst, const void *src, size_t bytes, hipStream
 hipError_t launch_export_rows(const int64_t *counts, const int64_t *rows, int64_t row, int n, int64_t *h_counts,
                               int64_t *h_rows, hipStream_t st);
 
+// NaN-aware argmin/argmax scan (f16, f32, f64 y): NaN skipped, chunk-major
+// like launch_scan, results in the same binres / partial slots.
+hipError_t launch_scan_nan(int y_dtype, const ScanParams &p, hipStream_t st);
+
 // EveryNth: out[i] = i*k for i < m, *count = m.
 hipError_t launch_everynth(int64_t k, int64_t m, int64_t *out, int64_t *count, hipStream_t st);
 // Gather of selected points, moved as raw words: xs, ys are the element sizes

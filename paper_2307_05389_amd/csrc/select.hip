@@ -27,6 +27,8 @@ __device__ inline void merge_one_bin(const MergeParams &p, int64_t bin, int lane
   }
   int64_t imn, imx;
   merged_bin(p, s, e, bin, lane, imn, imx);
+  if (imn == INT64_MAX) imn = s;  // only the NaN-aware scan leaves a bin without a value
+  if (imx == INT64_MAX) imx = s;
   if (lane == 0) p.cnt[bin] = bin_selection(s, e, imn, imx, p.m4, p.sel + 4 * bin);
 }
 
@@ -47,6 +49,8 @@ __global__ __launch_bounds__(256) void k_merge_lanes(MergeParams p) {
   }
   int64_t imn, imx;
   merged_bin_lane(p, s, e, bin, imn, imx);
+  if (imn == INT64_MAX) imn = s;
+  if (imx == INT64_MAX) imx = s;
   p.cnt[bin] = bin_selection(s, e, imn, imx, p.m4, p.sel + 4 * bin);
 }
 

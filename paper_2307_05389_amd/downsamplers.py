@@ -8,7 +8,9 @@ current HIP device, downsampled there and answered with a uint64 numpy array
 (the paper's return type); torch CUDA tensors stay on their device and the
 answer is a device int64 tensor.  `parallel` is accepted for interface
 compatibility and ignored: every call runs on the GPU.  MinMaxLTTB takes
-minmax_ratio (default 4, Sec. 4).
+minmax_ratio (default 4, Sec. 4).  NaNMinMaxDownsampler and NaNM4Downsampler
+skip NaN values of y (an all-NaN bin keeps its first index); the others
+require y without NaN.
 """
 import numpy as np
 import torch
@@ -76,6 +78,20 @@ class M4Downsampler(AbstractDownsampler):
 
     def _call(self, y, n_out, x):
         return api.m4(y, n_out, x=x)
+
+
+class NaNMinMaxDownsampler(AbstractDownsampler):
+    """MinMax with NaN values skipped; an all-NaN bin keeps its first index."""
+
+    def _call(self, y, n_out, x):
+        return api.nan_minmax(y, n_out, x=x)
+
+
+class NaNM4Downsampler(AbstractDownsampler):
+    """M4 with NaN values skipped in the argmin/argmax."""
+
+    def _call(self, y, n_out, x):
+        return api.nan_m4(y, n_out, x=x)
 
 
 class LTTBDownsampler(AbstractDownsampler):
