@@ -402,7 +402,27 @@ def bench_configs(reps_small=200, reps_big=10, check_oracle=True):
                 "then the gather of the selected (x, y)", "n": n, "n_out": 4000, "ms": round(ms, 4),
                 "ms_m4_alone": round(ms_m4, 4), "gather_values_match_indexing": ok})
     log(f"[bench] config m4+gather: {ms:.4f} ms (m4 alone {ms_m4:.4f} ms)")
-    del yd, xd, ws
+
+    # NaN-aware M4 on the same series with 1% of y set to NaN.
+    log("[bench] config nan_m4")
+    g = torch.Generator(device=dev)
+    g.manual_seed(11)
+    yd[torch.rand(n, device=dev, generator=g) < 0.01] = float("nan")
+    need = tsds.workspace_bytes("nan_m4", yd, 4000, x=xd)
+    wsn = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)
+    fn = lambda: tsds.downsample_into("nan_m4", yd, 4000, o, c, x=xd, workspace=wsn, stream=st)
+    ms = timed(fn, reps_big * 5)
+    parity = None
+    if check_oracle:
+        import oracle
+        got = o[: int(c.item())].cpu().numpy()
+        parity = "bit-exact" if np.array_equal(got, oracle.nan_m4(yd.cpu().numpy(), 4000, x=xd.cpu().numpy())) \
+            else "MISMATCH"
+    out.append({"algo": "nan_m4", "workload": "NaN-aware M4 with int64 x, float64 random walk with 1% NaN, N=1e8, "
+                "n_out=4000", "n": n, "n_out": 4000, "ms": round(ms, 4), "GBps": round(n * 8 / ms / 1e6, 1),
+                "frac_of_hbm_peak": round(n * 8 / ms / 1e6 / HBM_PEAK_GBS, 4), "parity_vs_oracle": parity})
+    log(f"[bench] config nan_m4: {ms:.4f} ms")
+    del yd, xd, ws, wsn
     torch.cuda.empty_cache()
     return out
 
