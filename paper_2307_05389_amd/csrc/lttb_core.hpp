@@ -163,7 +163,13 @@ __device__ inline double area2(double XA, double YA, double Xb, double Yb, doubl
   return __builtin_fabs((XA - Cx) * (Yb - YA) - (XA - Xb) * (Cy - YA));
 }
 
-__device__ inline int64_t points_m(const LttbParams &p) { return p.m >= 0 ? p.m : *p.m_dev; }
+// Point count: fixed, or read from the device (clamped to the capacity, so a
+// count never leads a kernel outside its buffers).
+__device__ inline int64_t points_m(const LttbParams &p) {
+  if (p.m >= 0) return p.m;
+  const int64_t m = *p.m_dev;
+  return m < 0 ? 0 : (m > p.m_max ? p.m_max : m);
+}
 
 // First point of bucket k (points [lo, hi)) with the largest area against
 // anchor A and centre k.
