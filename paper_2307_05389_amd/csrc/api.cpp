@@ -459,6 +459,10 @@ static MmlPlan mml_plan(const ts_series &s, int64_t n_out, int64_t ratio) {
   return p;
 }
 
+// Average candidates per bucket up to which the small-bucket map computes its
+// own centres (each anchor then re-reads at most a few points).
+static const int64_t kOwnCentresPerBucket = 8;
+
 static int run_lttb(const ts_series &s, const int64_t *sel, int64_t m, const int64_t *m_dev, int64_t m_max,
                     int64_t n_out, const LttbPlan &lp, void *ws, int64_t *out, int64_t *out_count, hipStream_t st) {
   LttbParams p{};
@@ -489,14 +493,18 @@ static int run_lttb(const ts_series &s, const int64_t *sel, int64_t m, const int
   p.out = out;
   p.out_count = out_count;
   hipError_t e;
-  if (sel) {
+  // Buckets of a few points (MinMaxLTTB's candidates): the map computes the
+  // centres it needs from the candidates directly, so neither the gather nor
+  // the centre pass runs first (two launches instead of four).
+  const bool own = lp.mode == kLttbSmall && m_max <= kOwnCentresPerBucket * (n_out - 2) + 2;
+  if (sel && !own) {
     p.gx = (uint64_t *)wsp(ws, lp.off_gx);
     p.gy = (uint64_t *)wsp(ws, lp.off_gy);
     if ((e = launch_lttb_gather(p, st)) != hipSuccess) return hip_fail(e, "lttb candidate gather");
   }
-  if ((e = launch_lttb_centres(p, st)) != hipSuccess) return hip_fail(e, "lttb centres");
+  if (!own && (e = launch_lttb_centres(p, st)) != hipSuccess) return hip_fail(e, "lttb centres");
   switch (lp.mode) {
-    case kLttbSmall: e = launch_lttb_small(p, st); break;
+    case kLttbSmall: e = launch_lttb_small(p, own, st); break;
     case kLttbHull:
       if ((e = launch_lttb_hull(p, st)) != hipSuccess) return hip_fail(e, "lttb hulls");
       e = launch_lttb_hull_walk(p, st);

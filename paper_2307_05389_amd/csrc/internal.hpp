@@ -137,7 +137,9 @@ hipError_t launch_lttb_gather(const LttbParams &p, hipStream_t st);
 hipError_t launch_lttb_hull(const LttbParams &p, hipStream_t st);
 hipError_t launch_lttb_hull_walk(const LttbParams &p, hipStream_t st);
 int64_t lttb_hull_group(int64_t nb);
-hipError_t launch_lttb_small(const LttbParams &p, hipStream_t st);
+// own_centres: the map computes each centre where it needs it (no centre
+// pass before it).
+hipError_t launch_lttb_small(const LttbParams &p, bool own_centres, hipStream_t st);
 hipError_t launch_lttb_seq(const LttbParams &p, hipStream_t st);
 
 }  // namespace tsds

@@ -343,12 +343,15 @@ hipError_t launch_lttb_gather(const LttbParams &p, hipStream_t st) {
 
 // The transition map of every anchor, one thread each over the whole GPU
 // (the map is the bulk of the small-bucket walk: a few dependent loads per
-// anchor through the candidate list), into p.next in global memory.
+// anchor through the candidate list), into p.next in global memory.  OWN:
+// each anchor computes the centre it needs itself (the same sequential
+// mean), so no centre pass runs before the map.
+template <bool OWN>
 __global__ __launch_bounds__(256) void k_lttb_map(LttbParams p) {
   const int64_t m = points_m(p);
   const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (m <= p.n_out || a >= m - 1) return;
-  p.next[a] = lttb_map_one(p, m, a, false);
+  p.next[a] = lttb_map_one(p, m, a, OWN);
 }
 
 // The walk along the map by one workgroup; next[] (copied from global) and
@@ -370,11 +373,15 @@ __global__ __launch_bounds__(1024) void k_lttb_small(LttbParams p, int32_t group
   lttb_walk_map(p, m, next, jump, group);
 }
 
-hipError_t launch_lttb_small(const LttbParams &p, hipStream_t st) {
+hipError_t launch_lttb_small(const LttbParams &p, bool own_centres, hipStream_t st) {
   const int32_t group = lttb_group_len(p.n_out - 2);
   const size_t lds = (size_t)p.m_max * 2 * sizeof(int32_t);
   const int lds_ok = lds <= 128 * 1024;
-  k_lttb_map<<<dim3((unsigned)((p.m_max + 255) / 256)), dim3(256), 0, st>>>(p);
+  const dim3 grid((unsigned)((p.m_max + 255) / 256));
+  if (own_centres)
+    k_lttb_map<true><<<grid, dim3(256), 0, st>>>(p);
+  else
+    k_lttb_map<false><<<grid, dim3(256), 0, st>>>(p);
   k_lttb_small<<<dim3(1), dim3(1024), lds_ok ? lds : 0, st>>>(p, group, lds_ok);
   return hipGetLastError();
 }
