@@ -186,7 +186,8 @@ int ts_gather(const ts_series *s, const int64_t *idx, const int64_t *count, int6
 
 /* ---- Batched mode: many series in one pass ---------------------------- */
 
-/* One task: a series, its algorithm (TS_MINMAX, TS_M4 or TS_MINMAXLTTB),
+/* One task: a series, its algorithm (TS_MINMAX, TS_M4, TS_MINMAXLTTB, or the
+ * NaN-aware TS_NAN_MINMAX / TS_NAN_M4 with ts_nan_minmax's semantics),
  * n_out, minmax_ratio (MinMaxLTTB only, 1..30) and the first slot of its
  * output in the batch's out_idx array (it writes up to n_out indices there
  * and its count to counts[task]). */

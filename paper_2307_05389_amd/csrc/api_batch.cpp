@@ -48,7 +48,7 @@ size_t batch_layout(ts_plan *p, int64_t chunk_bytes) {
   p->total_slots = 0;
   p->any_x = false;
   p->max_m = 0;
-  for (int g = 0; g < 22; g++) {
+  for (int g = 0; g < kBatchGroups; g++) {
     p->group_cb[g].clear();
     p->group_tix[g].clear();
     p->group_total[g] = 0;
@@ -59,7 +59,10 @@ size_t batch_layout(ts_plan *p, int64_t chunk_bytes) {
     BatchTask t;
     memset(&t, 0, sizeof t);
     const ts_series &s = in.series;
-    t.algo = in.algo;
+    // NaN-aware calls on integer y are the plain ones (no NaN to skip)
+    const bool fy = s.y_dtype == TS_F16 || s.y_dtype == TS_F32 || s.y_dtype == TS_F64;
+    t.algo = fy ? in.algo : in.algo == TS_NAN_MINMAX ? TS_MINMAX : in.algo == TS_NAN_M4 ? TS_M4 : in.algo;
+    const bool nan_task = t.algo == TS_NAN_MINMAX || t.algo == TS_NAN_M4;
     t.ydt = s.y_dtype;
     t.xdt = s.x ? s.x_dtype : TS_NONE;
     t.n_out = in.n_out;
@@ -86,11 +89,14 @@ size_t batch_layout(ts_plan *p, int64_t chunk_bytes) {
     int grp = 0;
     if (t.mode == 0) {
       const int64_t es = (int64_t)esize(t.ydt);
-      t.nb = in.algo == TS_MINMAX ? in.n_out / 2 : in.algo == TS_M4 ? in.n_out / 4 : in.n_out * in.minmax_ratio / 2;
+      t.nb = in.algo == TS_MINMAX || in.algo == TS_NAN_MINMAX ? in.n_out / 2
+             : in.algo == TS_M4 || in.algo == TS_NAN_M4     ? in.n_out / 4
+                                                             : in.n_out * in.minmax_ratio / 2;
       // bins averaging fewer than kStageBin elements: LDS-staged chunks
-      t.stage = t.n / t.nb < kStageBin ? 1 : 0;
+      // (the NaN-aware scan has no staged form)
+      t.stage = !nan_task && t.n / t.nb < kStageBin ? 1 : 0;
       t.chunk = (t.stage ? kStageChunk : chunk_bytes) / es;
-      grp = t.ydt + 11 * t.stage;
+      grp = nan_task ? 22 + t.ydt : t.ydt + 11 * t.stage;
       t.chunk_begin = p->group_total[grp];
       t.shift = (int64_t)(((uintptr_t)t.y & 15) / (uintptr_t)es);
       t.nchunks = (t.n + t.shift + t.chunk - 1) / t.chunk;
@@ -169,7 +175,7 @@ size_t batch_table_bytes(ts_plan *p) {
   const size_t b = al256(sizeof(int32_t) * p->slot_task.size());
   const size_t c = al256(sizeof(int32_t) * p->lttb_tasks.size());
   size_t need = a + b + c;
-  for (int g = 0; g < 22; g++) {
+  for (int g = 0; g < kBatchGroups; g++) {
     p->group_off_cb[g] = need;
     need += al256(sizeof(int64_t) * p->group_cb[g].size());
     p->group_off_tix[g] = need;
@@ -184,7 +190,7 @@ void batch_pack_table(const ts_plan *p, char *h) {
   memcpy(h, p->tasks.data(), sizeof(BatchTask) * p->tasks.size());
   memcpy(h + a, p->slot_task.data(), sizeof(int32_t) * p->slot_task.size());
   memcpy(h + a + b, p->lttb_tasks.data(), sizeof(int32_t) * p->lttb_tasks.size());
-  for (int g = 0; g < 22; g++) {
+  for (int g = 0; g < kBatchGroups; g++) {
     memcpy(h + p->group_off_cb[g], p->group_cb[g].data(), sizeof(int64_t) * p->group_cb[g].size());
     memcpy(h + p->group_off_tix[g], p->group_tix[g].data(), sizeof(int32_t) * p->group_tix[g].size());
   }
@@ -242,7 +248,7 @@ int tsds::batch_enqueue(const ts_plan *p, const void *d_table, int64_t *out, int
   if (p->any_x && (e = launch_batch_edges(a, st)) != hipSuccess) return api_fail(TS_ERR_HIP, "batch edges launch failed");
   // groups by bytes, largest first (the largest stays on st)
   std::vector<int> order;
-  for (int g = 0; g < 22; g++)
+  for (int g = 0; g < kBatchGroups; g++)
     if (p->group_total[g] > 0) order.push_back(g);
   std::stable_sort(order.begin(), order.end(), [p](int u, int v) {
     return p->group_total[u] * (int64_t)esize(u % 11) > p->group_total[v] * (int64_t)esize(v % 11);
@@ -264,7 +270,8 @@ int tsds::batch_enqueue(const ts_plan *p, const void *d_table, int64_t *out, int
     bg.ntasks = (int64_t)p->group_cb[g].size();
     bg.total = p->group_total[g];
     bg.ydt = g % 11;
-    bg.stage = g / 11;
+    bg.nan = g >= 22 ? 1 : 0;
+    bg.stage = g >= 22 ? 0 : g / 11;
     const hipStream_t s = (use_side && k > 0) ? p->side[(k - 1) % used] : st;
     if ((e = launch_batch_scan(a, bg, p->grid_blocks, s)) != hipSuccess)
       return api_fail(TS_ERR_HIP, "batch scan launch failed");
@@ -356,8 +363,9 @@ std::string signature(const ts_plan *p) {
 
 int tsds::batch_check_task(const ts_task &t) {
   int rc;
-  if (t.algo != TS_MINMAX && t.algo != TS_M4 && t.algo != TS_MINMAXLTTB)
-    return api_fail(TS_ERR_ARG, "batched tasks are MinMax, M4 or MinMaxLTTB");
+  if (t.algo != TS_MINMAX && t.algo != TS_M4 && t.algo != TS_MINMAXLTTB && t.algo != TS_NAN_MINMAX &&
+      t.algo != TS_NAN_M4)
+    return api_fail(TS_ERR_ARG, "batched tasks are MinMax, M4, MinMaxLTTB or their NaN-aware MinMax / M4");
   if ((rc = api_check_series(&t.series)) || (rc = api_check_nout(t.algo, t.n_out, t.minmax_ratio))) return rc;
   if (t.algo == TS_MINMAXLTTB && t.minmax_ratio > 30)
     return api_fail(TS_ERR_ARG, "batched MinMaxLTTB needs minmax_ratio <= 30");

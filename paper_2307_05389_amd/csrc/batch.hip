@@ -23,6 +23,7 @@
 #include "internal.hpp"
 #include "scan_core.hpp"
 #include "select_core.hpp"
+#include "batch_core.hpp"
 
 namespace tsds {
 
@@ -41,29 +42,6 @@ __device__ inline ScanParams task_scan_params(const BatchArgs &a, const BatchTas
   sp.small = small;
   sp.variant = 3;
   sp.stage = t.stage;
-  sp.x = nullptr;
-  sp.xedges = nullptr;
-  sp.xclass = 0;
-  return sp;
-}
-
-// The same, with every field read from the task table made wave-uniform.
-__device__ inline ScanParams task_scan_params_uniform(char *ws, const BatchTask *__restrict__ t, int32_t small) {
-  ScanParams sp;
-  sp.y = uniform(t->y);
-  sp.n = uniform(t->n);
-  sp.shift = uniform(t->shift);
-  sp.chunk = uniform(t->chunk);
-  sp.nchunks = uniform(t->nchunks);
-  const void *x = uniform(t->x);
-  sp.edges = x ? (const int64_t *)(ws + uniform(t->o_edges)) : nullptr;
-  sp.nb = uniform(t->nb);
-  sp.binres = (int64_t *)(ws + uniform(t->o_binres));
-  sp.partL = (Partial *)(ws + uniform(t->o_partL));
-  sp.partR = (Partial *)(ws + uniform(t->o_partR));
-  sp.small = small;
-  sp.variant = 3;
-  sp.stage = uniform(t->stage);
   sp.x = nullptr;
   sp.xedges = nullptr;
   sp.xclass = 0;
@@ -98,24 +76,6 @@ hipError_t launch_batch_edges(const BatchArgs &a, hipStream_t st) {
   if (a.total_slots == 0) return hipSuccess;
   k_batch_edges<<<dim3((unsigned)((a.total_slots + 3) / 4)), dim3(256), 0, st>>>(a);
   return hipGetLastError();
-}
-
-// Position k in the group's task list of the last task whose first work item
-// is <= item (tasks without items share their successor's start).
-__device__ int64_t group_pos_of_item(const int64_t *__restrict__ cb, int64_t ntasks, int64_t item, int lane) {
-  int64_t lo = 0, hi = ntasks;  // cb[lo] <= item < cb[hi]
-  while (hi - lo > 1) {
-    const int64_t step = (hi - lo + 63) / 64;
-    const int64_t q = lo + (int64_t)lane * step;
-    const bool le = q < hi && cb[q] <= item;
-    const int cnt = __builtin_popcountll(ballot(le));
-    const int64_t nlo = lo + (int64_t)(cnt - 1) * step;
-    const int64_t nhi = lo + (int64_t)cnt * step;
-    lo = nlo;
-    hi = nhi < hi ? nhi : hi;
-  }
-  while (lo + 1 < ntasks && uniform(cb[lo + 1]) <= item) lo++;
-  return lo;
 }
 
 // Persistent scan over one dtype group: a fixed grid of wavefronts, each
@@ -163,6 +123,7 @@ __global__ __launch_bounds__(256) void k_batch_scan_staged(const BatchTask *__re
 }
 
 hipError_t launch_batch_scan(const BatchArgs &a, const BatchGroup &g, int64_t grid_blocks, hipStream_t st) {
+  if (g.nan) return launch_batch_scan_nan(a, g, grid_blocks, st);
   if (g.total == 0) return hipSuccess;
   int64_t gb = grid_blocks;
   if (gb > (g.total + 3) / 4) gb = (g.total + 3) / 4;
@@ -221,7 +182,7 @@ __device__ inline MergeParams task_merge_params(const BatchArgs &a, const BatchT
   mp.binres = (const int64_t *)(a.ws + t.o_binres);
   mp.partL = (const Partial *)(a.ws + t.o_partL);
   mp.partR = (const Partial *)(a.ws + t.o_partR);
-  mp.m4 = t.algo == TS_M4;
+  mp.m4 = t.algo == TS_M4 || t.algo == TS_NAN_M4;
   mp.sel = (int64_t *)(a.ws + t.o_sel);
   mp.cnt = (int64_t *)(a.ws + t.o_cnt);
   return mp;
@@ -246,6 +207,8 @@ __global__ __launch_bounds__(256) void k_batch_merge(BatchArgs a) {
   }
   int64_t imn, imx;
   merged_bin(mp, s, e, bin, lane, imn, imx);
+  if (imn == INT64_MAX) imn = s;  // only NaN-aware tasks leave a bin without a value
+  if (imx == INT64_MAX) imx = s;
   if (lane == 0) mp.cnt[bin] = bin_selection(s, e, imn, imx, mp.m4, mp.sel + 4 * bin);
 }
 
@@ -264,6 +227,8 @@ __global__ __launch_bounds__(256) void k_batch_merge_lanes(BatchArgs a) {
   }
   int64_t imn, imx;
   merged_bin_lane(mp, s, e, bin, imn, imx);
+  if (imn == INT64_MAX) imn = s;
+  if (imx == INT64_MAX) imx = s;
   mp.cnt[bin] = bin_selection(s, e, imn, imx, mp.m4, mp.sel + 4 * bin);
 }
 

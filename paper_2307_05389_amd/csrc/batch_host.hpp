@@ -10,18 +10,21 @@
 #include "internal.hpp"
 #include "tsds.h"
 
+// Work-list groups: g = dtype + 11 * staged for the plain scan, 22 + dtype
+// for NaN-aware tasks (floating-point y only).
+constexpr int kBatchGroups = 33;
+
 struct ts_plan {
   std::vector<ts_task> in;
   std::vector<tsds::BatchTask> tasks;
   std::vector<int32_t> slot_task, lttb_tasks;
   int64_t total_chunks = 0, total_slots = 0;
   int64_t wave_slots = 0;   // slots of tasks merged a wavefront per bin come first
-  // per (element type, staged): task list and first work items; group
-  // g = dtype + 11 * staged
-  std::vector<int64_t> group_cb[22];
-  std::vector<int32_t> group_tix[22];
-  int64_t group_total[22] = {0};
-  size_t group_off_cb[22] = {0}, group_off_tix[22] = {0};
+  // per group (see kBatchGroups): task list and first work items
+  std::vector<int64_t> group_cb[kBatchGroups];
+  std::vector<int32_t> group_tix[kBatchGroups];
+  int64_t group_total[kBatchGroups] = {0};
+  size_t group_off_cb[kBatchGroups] = {0}, group_off_tix[kBatchGroups] = {0};
   size_t ws_bytes = 0;      // for the largest chunk count in the tuning space
   int64_t out_needed = 0;   // max(out_offset + n_out)
   bool any_x = false;

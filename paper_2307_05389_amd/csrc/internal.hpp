@@ -153,7 +153,7 @@ struct BatchTask {
   const void *x;        // NULL if no x
   int64_t n;
   int32_t ydt, xdt;
-  int32_t algo;         // TS_MINMAX, TS_M4, TS_MINMAXLTTB
+  int32_t algo;         // TS_MINMAX, TS_M4, TS_MINMAXLTTB, TS_NAN_MINMAX, TS_NAN_M4 (NaN-aware only for float y)
   int32_t mode;         // 0: scan; 1: n <= n_out (all indices); 2: MinMaxLTTB without preselection
   int32_t stage;        // 1: staged chunks (many small bins)
   int32_t pad_;
@@ -194,9 +194,11 @@ struct BatchGroup {
   int64_t total;
   int32_t ydt;
   int32_t stage;
+  int32_t nan;     // NaN-aware tasks (floating-point y)
 };
 
 hipError_t launch_batch_scan(const BatchArgs &a, const BatchGroup &g, int64_t grid_blocks, hipStream_t st);
+hipError_t launch_batch_scan_nan(const BatchArgs &a, const BatchGroup &g, int64_t grid_blocks, hipStream_t st);
 hipError_t launch_batch_merge(const BatchArgs &a, hipStream_t st);
 hipError_t launch_batch_compact(const BatchArgs &a, hipStream_t st);
 hipError_t launch_batch_lttb(const BatchArgs &a, hipStream_t st);

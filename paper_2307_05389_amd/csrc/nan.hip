@@ -22,6 +22,7 @@
 #include "common.hpp"
 #include "internal.hpp"
 #include "scan_core.hpp"
+#include "batch_core.hpp"
 
 namespace tsds {
 
@@ -145,6 +146,41 @@ __global__ __launch_bounds__(256) void k_scan_nan(ScanParams p) {
   const int64_t c = uniform((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6));
   if (c >= p.nchunks) return;
   scan_chunk_nan<T>(p, c, lane_id());
+}
+
+// Batched mode: the persistent scan over one element type's NaN-aware tasks
+// (same work split and task lookup as k_batch_scan).
+template <typename T>
+__global__ __launch_bounds__(256) void k_batch_scan_nan(const BatchTask *__restrict__ tasks,
+                                                        const int64_t *__restrict__ cb,
+                                                        const int32_t *__restrict__ tix, int64_t ntasks,
+                                                        int64_t total, char *ws) {
+  const int lane = lane_id();
+  const int64_t W = (int64_t)gridDim.x * 4;
+  const int64_t w = uniform((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6));
+  const int64_t i0 = total * w / W, i1 = total * (w + 1) / W;
+#pragma nounroll
+  for (int64_t item = i0; item < i1; item++) {
+    const int64_t k = uniform(group_pos_of_item(cb, ntasks, item, lane));
+    const BatchTask *tk = tasks + uniform(tix[k]);
+    const ScanParams sp = task_scan_params_uniform(ws, tk, 0);
+    scan_chunk_nan<T>(sp, item - uniform(tk->chunk_begin), lane);
+  }
+}
+
+hipError_t launch_batch_scan_nan(const BatchArgs &a, const BatchGroup &g, int64_t grid_blocks, hipStream_t st) {
+  if (g.total == 0) return hipSuccess;
+  int64_t gb = grid_blocks;
+  if (gb > (g.total + 3) / 4) gb = (g.total + 3) / 4;
+  if (gb < 1) gb = 1;
+  const dim3 grid((unsigned)gb), block(256);
+  switch (g.ydt) {
+    case TS_F16: k_batch_scan_nan<half_t><<<grid, block, 0, st>>>(a.tasks, g.cb, g.tix, g.ntasks, g.total, a.ws); break;
+    case TS_F32: k_batch_scan_nan<float><<<grid, block, 0, st>>>(a.tasks, g.cb, g.tix, g.ntasks, g.total, a.ws); break;
+    case TS_F64: k_batch_scan_nan<double><<<grid, block, 0, st>>>(a.tasks, g.cb, g.tix, g.ntasks, g.total, a.ws); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_scan_nan(int ydt, const ScanParams &p, hipStream_t st) {

@@ -142,3 +142,51 @@ def test_nan_downsampler_classes(ts, oracle_mod, cls, kind):
     got = getattr(ts, cls)().downsample(y, n_out=400)
     assert got.dtype == np.uint64
     assert np.array_equal(got.astype(np.int64), getattr(oracle_mod, "nan_" + kind)(y, 400))
+
+
+def test_nan_batched(ts, oracle_mod):
+    """NaN-aware MinMax / M4 tasks in one batch with plain tasks: each task
+    equals the oracle and the single call, eager and replayed from a graph,
+    at two chunk sizes."""
+    rng = np.random.default_rng(5)
+    specs = []
+    dts = [np.float32, np.float16, np.float64, np.int16]
+    for i in range(24):
+        L = int(np.exp(rng.uniform(np.log(100), np.log(4e5))))
+        dt = dts[i % 4]
+        y = S.walk(L, dt, seed=300 + i)
+        if dt != np.int16:
+            y = with_nan(y, [0.0, 0.05, 0.6, 1.0][(i // 4) % 4], seed=400 + i, runs=bool(i % 2))
+        algo = ["nan_minmax", "nan_m4", "minmax" if dt == np.int16 else "nan_m4"][i % 3]
+        n_out = int(rng.integers(8, 1200))
+        n_out = 4 * (n_out // 4) if algo.endswith("m4") else 2 * (n_out // 2)
+        x = S.timestamps(L, 100, seed=500 + i) if i % 5 == 2 else None
+        specs.append(dict(algo=algo, y=y, x=x, n_out=n_out))
+    dev_specs = []
+    for s in specs:
+        d = dict(s)
+        d["y"] = dev(s["y"])
+        d["x"] = None if s["x"] is None else dev(s["x"])
+        dev_specs.append(d)
+    b = ts.Batch(dev_specs)
+    try:
+        for chunk, graph in ((-1, False), (-1, True), (4096, True)):
+            if chunk > 0:
+                cb, sb, gb = b.tuning()
+                b.set_tuning(chunk, sb, gb)
+            b.out.fill_(-7)
+            b.run(graph=graph)
+            b.run(graph=graph)
+            res = [r.cpu().numpy() for r in b.results()]
+            for i, (s, d) in enumerate(zip(specs, dev_specs)):
+                say("nan batch", chunk, graph, i, s["algo"], np.dtype(s["y"].dtype).name, len(s["y"]), s["n_out"])
+                if s["algo"].startswith("nan_"):
+                    exp = getattr(oracle_mod, s["algo"])(s["y"], s["n_out"], x=s["x"])
+                    one = getattr(ts, s["algo"])(d["y"], s["n_out"], x=d["x"]).cpu().numpy()
+                else:
+                    exp = getattr(oracle_mod, s["algo"])(s["y"], s["n_out"], x=s["x"])
+                    one = getattr(ts, s["algo"])(d["y"], s["n_out"], x=d["x"]).cpu().numpy()
+                assert np.array_equal(res[i], exp), (chunk, graph, i)
+                assert np.array_equal(res[i], one), (chunk, graph, i)
+    finally:
+        b.close()
