@@ -48,6 +48,11 @@ def test_workspace_bytes_host_logic(L):
     assert L.ts_workspace_bytes(0, ctypes.byref(_series(100)), 1000, 0) == 0  # n <= n_out
     assert L.ts_workspace_bytes(3, ctypes.byref(_series(10**7)), 1000, 4) > 0
     assert L.ts_workspace_bytes(3, ctypes.byref(_series(10**7)), 1001, 1) == 0  # odd n_out*ratio
+    # NaN-aware MinMax / M4 (algos 4, 5): same n_out rules, their own chunking
+    for algo, ok, bad in ((4, 1000, 1001), (5, 4000, 4002)):
+        w = L.ts_workspace_bytes(algo, ctypes.byref(_series(10**8, ydt=10)), ok, 0)
+        assert w > 0 and w % 256 == 0
+        assert L.ts_workspace_bytes(algo, ctypes.byref(_series(10**8, ydt=10)), bad, 0) == 0
 
 
 @pytest.mark.parametrize("call,code", [
