@@ -28,8 +28,8 @@ def ts():
 
 
 def with_nan(y, frac, seed, runs=False):
-    """NaN at a fraction of the points (quiet and negative NaN, and a
-    signalling pattern for f32/f64), optionally as long runs."""
+    """NaN at a fraction of the points, optionally as long runs; with any NaN,
+    also a negative and a signalling NaN bit pattern of the type."""
     y = y.copy()
     n = len(y)
     rng = np.random.default_rng(seed)
@@ -39,10 +39,11 @@ def with_nan(y, frac, seed, runs=False):
             y[a: a + int(rng.integers(1, max(2, n // 10)))] = np.nan
     else:
         y[rng.random(n) < frac] = np.nan
-    if n > 8 and y.dtype in (np.float32, np.float64):
-        bits = y.view(np.uint32 if y.dtype == np.float32 else np.uint64)
-        neg_nan = 0xFFC00000 if y.dtype == np.float32 else 0xFFF8000000000000
-        snan = 0x7F800001 if y.dtype == np.float32 else 0x7FF0000000000001
+    if n > 8 and frac > 0:
+        ut = {np.dtype(np.float16): np.uint16, np.dtype(np.float32): np.uint32, np.dtype(np.float64): np.uint64}
+        bits = y.view(ut[y.dtype])
+        neg_nan = {2: 0xFE00, 4: 0xFFC00000, 8: 0xFFF8000000000000}[y.itemsize]
+        snan = {2: 0x7C01, 4: 0x7F800001, 8: 0x7FF0000000000001}[y.itemsize]
         bits[n // 3] = neg_nan
         bits[n // 2] = snan
     return y
