@@ -257,10 +257,15 @@ __device__ inline void copy_map(const int32_t *src, int32_t *dst, int64_t cnt) {
 // workgroup, from the transition map next[] (entries 0 .. m-2; see
 // lttb_map_one).  jump[] holds m int32 (LDS or global); it takes the group
 // exits, then the picks of the buckets (nb < m).
+constexpr int64_t kWalkEntriesLds = 2048;
+
 __device__ void lttb_walk_map(const LttbParams &p, int64_t m, const int32_t *next, int32_t *jump, int32_t group) {
   const int64_t nb = p.n_out - 2;
-  int32_t *entry = p.entry;
   const int64_t G = (nb + group - 1) / group;
+  // group entries: in LDS when they fit (read back right after the chain),
+  // else the workspace copy
+  __shared__ int32_t s_entry[kWalkEntriesLds];
+  int32_t *entry = G <= kWalkEntriesLds ? s_entry : p.entry;
 
   // 1. group exits: for every possible entry a of group g (the first point
   //    for g = 0, else any point of bucket g*group - 1), follow next[] over
