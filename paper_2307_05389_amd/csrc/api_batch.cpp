@@ -233,7 +233,7 @@ BatchArgs args(const ts_plan *p, const void *d_table, int64_t *out, int64_t *cou
   a.counts = counts;
   a.small = p->small;
   a.max_m = p->max_m;
-  a.lds_m = 16384;
+  a.lds_m = kWalkMapLds / 8;
   a.lds_ok = p->max_m <= a.lds_m ? 1 : 0;
   if (a.lds_ok) a.lds_m = std::max<int64_t>(p->max_m, 1);
   return a;

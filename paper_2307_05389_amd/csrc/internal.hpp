@@ -125,6 +125,11 @@ struct LttbParams {
   int32_t *hflag;         // [1] 1 when the map walk has written the result
 };
 
+// LDS of the small-bucket walk: its own tables (19 KB) plus the map next[]
+// and jump[] (8 bytes per point, at most kWalkMapLds), within 144 KB per
+// workgroup; larger maps stay in the workspace.
+constexpr int64_t kWalkMapLds = 124 * 1024;
+
 // Hull-pruned plain LTTB: used for buckets of at least kHullMinBucket points;
 // at most kHullCand candidates are kept per bucket (else the bucket is walked
 // in full) and kHullLane hull points per lane segment.

@@ -376,7 +376,7 @@ __global__ __launch_bounds__(1024) void k_lttb_small(LttbParams p, int32_t group
 hipError_t launch_lttb_small(const LttbParams &p, bool own_centres, hipStream_t st) {
   const int32_t group = lttb_group_len(p.n_out - 2);
   const size_t lds = (size_t)p.m_max * 2 * sizeof(int32_t);
-  const int lds_ok = lds <= 128 * 1024;
+  const int lds_ok = lds <= kWalkMapLds;
   const dim3 grid((unsigned)((p.m_max + 255) / 256));
   if (own_centres)
     k_lttb_map<true><<<grid, dim3(256), 0, st>>>(p);

@@ -258,6 +258,8 @@ __device__ inline void copy_map(const int32_t *src, int32_t *dst, int64_t cnt) {
 // lttb_map_one).  jump[] holds m int32 (LDS or global); it takes the group
 // exits, then the picks of the buckets (nb < m).
 constexpr int64_t kWalkEntriesLds = 2048;
+constexpr int64_t kWalkSuperLds = 2048;  // super-group exits (super-groups x entries each)
+constexpr int64_t kWalkSupers = 256;
 
 __device__ void lttb_walk_map(const LttbParams &p, int64_t m, const int32_t *next, int32_t *jump, int32_t group) {
   const int64_t nb = p.n_out - 2;
@@ -284,8 +286,49 @@ __device__ void lttb_walk_map(const LttbParams &p, int64_t m, const int32_t *nex
   }
   __syncthreads();
 
-  // 2. chain over groups.
-  if (threadIdx.x == 0) {
+  // 2. chain over groups.  With many groups, in two levels: super-groups of
+  //    T groups get their exits for every possible entry in parallel (2a),
+  //    one thread chains the H super-groups (2b), and each super-group's
+  //    group entries follow in parallel (2c): 2T + H dependent reads
+  //    instead of G.
+  int64_t T = 1;
+  while (T * T < G) T++;
+  const int64_t H = (G + T - 1) / T;
+  __shared__ int32_t s_sup[kWalkSuperLds];
+  __shared__ int64_t s_slo[kWalkSupers];
+  __shared__ int32_t s_sent[kWalkSupers];
+  if (T > 1 && H <= kWalkSupers && H * P <= kWalkSuperLds) {
+    for (int64_t h = threadIdx.x; h < H; h += blockDim.x)
+      s_slo[h] = h == 0 ? 0 : bucket_start(h * T * group - 1, m, nb);
+    for (int64_t idx = threadIdx.x; idx < H * P; idx += blockDim.x) {
+      const int64_t h = idx / P, off = idx % P;
+      const int64_t lo = h == 0 ? 0 : bucket_start(h * T * group - 1, m, nb);
+      const int64_t hi = h == 0 ? 1 : bucket_start(h * T * group, m, nb);
+      const int64_t a = lo + off;
+      if (a >= hi) continue;
+      const int64_t g1 = (h + 1) * T < G ? (h + 1) * T : G;
+      int32_t v = (int32_t)a;
+      for (int64_t g = h * T; g < g1; g++) v = jump[v];
+      s_sup[idx] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int32_t v = 0;
+      for (int64_t h = 0; h < H; h++) {
+        s_sent[h] = v;
+        v = s_sup[h * P + (v - s_slo[h])];
+      }
+    }
+    __syncthreads();
+    for (int64_t h = threadIdx.x; h < H; h += blockDim.x) {
+      int32_t v = s_sent[h];
+      const int64_t g1 = (h + 1) * T < G ? (h + 1) * T : G;
+      for (int64_t g = h * T; g < g1; g++) {
+        entry[g] = v;
+        v = jump[v];
+      }
+    }
+  } else if (threadIdx.x == 0) {
     int32_t v = 0;
     for (int64_t g = 0; g < G; g++) {
       entry[g] = v;
@@ -322,9 +365,11 @@ __device__ void lttb_small_walk(const LttbParams &p, int64_t m, int32_t *next, i
   lttb_walk_map(p, m, next, jump, group);
 }
 
+// Buckets per group of the walk: the smallest power of two S with 2 S^3 >= nb
+// (the group and super-group chains then stay near nb^(1/3) each).
 __host__ __device__ inline int32_t lttb_group_len(int64_t nb) {
   int32_t group = 1;
-  while ((int64_t)group * group * 2 < nb) group *= 2;
+  while ((int64_t)group * group * group * 2 < nb) group *= 2;
   return group;
 }
 
