@@ -326,6 +326,20 @@ def test_lttb_parity(ts, oracle_mod, dtype, with_x):
         assert near == 0 and np.array_equal(got, exp)
 
 
+@pytest.mark.parametrize("n,n_out", [
+    (10, 3),                  # one group: one chain
+    (300, 102),               # two-level chain, entries in LDS
+    (2_000_000, 200_002),     # > 2,048 groups (entries in the workspace), two-level chain
+    (32_000_000, 1_000_002),  # buckets of 32: too many super-group entries for LDS, one chain
+])
+def test_lttb_small_walk_levels(ts, oracle_mod, n, n_out):
+    """The small-bucket walk's group chain in each of its forms, bit-exact."""
+    y = S.walk(n, np.float32, seed=n % 97)
+    say(f"[lttb walk] n={n} n_out={n_out}")
+    got = gpu(ts, "lttb", y, n_out)
+    assert np.array_equal(got, orc(oracle_mod, "lttb", y, n_out))
+
+
 def hull_cases(n, dtype, seed):
     """Series for the hull-pruned LTTB walk: a random walk, the same with long
     constant runs (exact area ties), a constant series (every area zero) and
