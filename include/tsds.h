@@ -178,7 +178,8 @@ int ts_everynth(const ts_series *s, int64_t n_out, int64_t *out_idx, int64_t *ou
  * y_out[i] = y[idx[i]] and, when x_out is not NULL, x_out[i] = x[idx[i]],
  * in the series' own element types.  idx, count: device int64 (typically a
  * downsampler's out_idx / out_count, read on the device, so no host sync is
- * needed); y_out, x_out: device buffers of cap elements aligned to their
+ * needed); idx holds at least min(*count, cap) entries (a negative count
+ * gathers nothing); y_out, x_out: device buffers of cap elements aligned to their
  * element size.  x_out must be NULL when the series has no x.  An index
  * outside [0, n) writes nothing at its position.  cap = 0 enqueues nothing. */
 int ts_gather(const ts_series *s, const int64_t *idx, const int64_t *count, int64_t cap, void *x_out,
