@@ -119,3 +119,28 @@ def test_batch_autotune_keeps_results(ts, tmp_path):
     assert b2.autotune(cache) == t1        # served from the cache
     b.close()
     b2.close()
+
+
+def test_batch_walk_maps_beyond_64k_lds(ts, oracle_mod):
+    """MinMaxLTTB tasks whose walk maps need more than 64 KB of LDS (12,002
+    candidates: 96 KB; 15,866: 124 KB) next to small ones, against the oracle
+    and the plain call."""
+    specs = [dict(algo="minmaxlttb", y=S.walk(1_000_003, np.float32, 81), x=None, n_out=3000, minmax_ratio=4),
+             dict(algo="minmaxlttb", y=S.walk(200_000, np.int16, 82), x=S.timestamps(200_000, 50, seed=83),
+                  n_out=1500, minmax_ratio=4),
+             dict(algo="minmax", y=S.walk(50_000, np.uint8, 84), x=None, n_out=1000)]
+    for tail in (None, dict(algo="minmaxlttb", y=S.walk(600_000, np.float64, 85), x=None, n_out=3966,
+                             minmax_ratio=4)):
+        sp = specs + ([tail] if tail else [])
+        dev = to_dev(sp)
+        b = ts.Batch(dev)
+        for graph in (False, True):
+            say(f"[batch lds] {len(sp)} tasks graph={graph}")
+            b.run(graph=graph)
+            res = [r.cpu().numpy() for r in b.results()]
+            for i, (s, d) in enumerate(zip(sp, dev)):
+                assert np.array_equal(res[i], oracle_of(oracle_mod, s)), i
+                if s["algo"] == "minmaxlttb":
+                    plain = ts.minmaxlttb(d["y"], s["n_out"], x=d["x"], minmax_ratio=s["minmax_ratio"])
+                    assert np.array_equal(res[i], plain.cpu().numpy()), i
+        b.close()

@@ -376,19 +376,26 @@ def test_lttb_hull_walk(ts, oracle_mod, dtype):
                 say(f"[lttb hull] {np.dtype(dtype).name} {name} x={xname} n_out={n_out}")
                 got = gpu(ts, "lttb", y, n_out, x)
                 near = stepwise_check(oracle_mod, y, n_out, got, x=x)
-                if near:
-                    say(f"    near-tie acceptances: {near}")
+                say(f"    near-tie acceptances: {near}")
+                # the hull keeps every point that can reach the maximum, so the
+                # walk is the oracle's step for step, with no tolerance used
+                assert near == 0 and np.array_equal(got, orc(oracle_mod, "lttb", y, n_out, x))
     y = S.walk(100_000, dtype, seed=67)
     say(f"[lttb hull] {np.dtype(dtype).name} MinMaxLTTB keeping every point")
     got = gpu(ts, "minmaxlttb", y, 150, None, 1000)
-    stepwise_check(oracle_mod, y, 150, got)
+    near = stepwise_check(oracle_mod, y, 150, got)
+    say(f"    near-tie acceptances: {near}")
+    assert near == 0
 
 
 @pytest.mark.parametrize("dtype", [np.float32, np.float64, np.int16, np.uint8, np.float16])
 @pytest.mark.parametrize("xname", ["none", "i64", "f64"])
 def test_minmaxlttb_parity(ts, oracle_mod, dtype, xname):
+    # (1_000_003, 3000, 4) and (500_000, 3966, 4): the walk's maps take 96 KB
+    # and 124 KB of LDS; (500_000, 3970, 4): just over, maps in global memory
     for n, n_out, ratio in ((100000, 500, 4), (1_000_003, 2000, 4), (30000, 1000, 8), (5000, 1000, 4),
-                            (4000, 1000, 4), (250000, 3, 2)):
+                            (4000, 1000, 4), (250000, 3, 2), (1_000_003, 3000, 4), (500_000, 3966, 4),
+                            (500_000, 3970, 4)):
         y = S.walk(n, dtype, seed=n % 13)
         x = xs_for(n, 3)[xname]
         say(f"[mmlttb] {np.dtype(dtype).name} x={xname} n={n} n_out={n_out} r={ratio}")

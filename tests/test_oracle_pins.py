@@ -319,6 +319,126 @@ def test_lttb_centres_are_bucket_means(oracle_mod):
     assert cx[-1] == float(x[-1]) and cy[-1] == float(y[-1])
 
 
+def _float_mean_cases(ydt, xdt, seed):
+    """A walk in y (float dtype ydt), optional float x (xdt) that crosses zero,
+    and two buckets forced to (nearly) cancel: one in y (+-A pairs plus a small
+    residue) and, through x's sign change, one in x."""
+    m, n_out = 20_000, 40
+    y = S.walk(m, ydt, seed=seed).astype(np.float64)
+    nb = n_out - 2
+    b = [1 + (k * (m - 2)) // nb for k in range(nb + 1)]
+    lo, hi = b[7], b[8]
+    rng = np.random.default_rng(seed + 1)
+    big = (1000.0 + rng.random((hi - lo) // 2) * 500.0)
+    canc = np.zeros(hi - lo)
+    canc[0:2 * len(big):2] = big
+    canc[1:2 * len(big):2] = -big
+    canc[-1] += 0.375
+    y[lo:hi] = canc
+    y = y.astype(ydt)
+    x = None
+    if xdt is not None:
+        # strictly increasing, from about -m/2 to m/2 (quarter steps)
+        x = ((S.timestamps(m, 3, seed=seed + 2).astype(np.float64) - 1.0 * m) * 0.25).astype(xdt)
+    return y, x, n_out
+
+
+def _exact_mean_and_scale(vals):
+    """Exact rational mean of the doubles in vals, and the mean of their
+    absolute values (the scale the mean error is measured against)."""
+    from fractions import Fraction
+    fr = [Fraction(float(v)) for v in vals]
+    n = len(fr)
+    return sum(fr, Fraction(0)) / n, sum((abs(v) for v in fr), Fraction(0)) / n
+
+
+@pytest.mark.parametrize("ydt", [np.float16, np.float32, np.float64])
+@pytest.mark.parametrize("xdt", [None, np.float32, np.float64])
+@pytest.mark.parametrize("use_sel", [False, True])
+def test_lttb_float_centres_near_exact_means(oracle_mod, ydt, xdt, use_sel):
+    """Float coordinates (Sec. 4: LTTB's next-bucket means): each centre is
+    within 1e-12 of the exact rational bucket mean, measured relative to the
+    bucket's mean absolute value (which is the mean itself when the values
+    share a sign, and stays meaningful for a bucket that cancels to ~0).
+    Accumulating in float32, dropping a term, or averaging the wrong bucket
+    misses this by many orders of magnitude."""
+    from fractions import Fraction
+    y, x, n_out = _float_mean_cases(ydt, xdt, seed=30 + 3 * ALL_DTYPES.index(ydt))
+    m = len(y)
+    sel = None
+    if use_sel:
+        # MinMaxLTTB's candidate set (first point, interior MinMax, last point)
+        sel = oracle_mod.minmaxlttb_candidates(y, 1000, 8, x=x)
+    cx, cy = oracle_mod.lttb_centres(y, n_out, x=x, sel=sel)
+    idx = np.arange(m) if sel is None else sel
+    mp = len(idx)
+    nb = n_out - 2
+    b = [1 + (k * (mp - 2)) // nb for k in range(nb + 1)]
+    X = (idx.astype(np.float64) if x is None else x[idx].astype(np.float64))
+    Y = y[idx].astype(np.float64)
+    worst = 0.0
+    for k in range(nb - 1):
+        lo, hi = b[k + 1], b[k + 2]
+        for got, vals in ((cx[k], X[lo:hi]), (cy[k], Y[lo:hi])):
+            mu, scale = _exact_mean_and_scale(vals)
+            err = abs(Fraction(float(got)) - mu)
+            assert err <= Fraction(1, 10**12) * scale, (k, float(got), float(mu))
+            if scale:
+                worst = max(worst, float(err / scale))
+    # the last bucket's centre is the last point itself
+    assert cx[-1] == X[-1] and cy[-1] == Y[-1]
+    print(f"max mean error / mean |v|: {worst:.3g}")
+
+
+def test_lttb_cancelling_bucket_is_present():
+    """The float-mean cases above really contain a bucket whose exact mean is
+    tiny next to its values (so a relative-to-the-mean check would be
+    meaningless there, and the scale matters)."""
+    y, _, n_out = _float_mean_cases(np.float32, None, seed=33)
+    m, nb = len(y), n_out - 2
+    b = [1 + (k * (m - 2)) // nb for k in range(nb + 1)]
+    mu, scale = _exact_mean_and_scale(y[b[7]:b[8]])
+    assert abs(mu) < scale / 1000
+
+
+def test_lttb_step_areas_match_exact_areas(oracle_mod):
+    """oracle.lttb_step's areas (the step-wise checker's inputs): for every
+    point of every bucket, the doubled area the oracle reports is the exact
+    rational |cross(P_b - A, C - A)| of the same doubles, up to the rounding
+    of four subtractions, two products and one difference; the pick's area is
+    the largest, reached first."""
+    from fractions import Fraction
+    rng = np.random.default_rng(41)
+    for trial in range(6):
+        m = int(rng.integers(30, 300))
+        n_out = int(rng.integers(4, m // 3))
+        y = S.walk(m, (np.float32, np.float64, np.int16)[trial % 3], seed=50 + trial)
+        x = None if trial % 2 == 0 else np.cumsum(rng.integers(1, 7, m)).astype(np.float64) * 0.5
+        walk = oracle_mod.lttb(y, n_out, x=x)
+        cx, cy = oracle_mod.lttb_centres(y, n_out, x=x)
+        nb = n_out - 2
+        b = [1 + (k * (m - 2)) // nb for k in range(nb + 1)]
+        X = np.arange(m, dtype=np.float64) if x is None else x.astype(np.float64)
+        Y = y.astype(np.float64)
+        for k in range(nb):
+            A = int(walk[k])
+            C = (Fraction(float(cx[k])), Fraction(float(cy[k])))
+            XA, YA = Fraction(float(X[A])), Fraction(float(Y[A]))
+            areas = []
+            for j in range(b[k], b[k + 1]):
+                pick, best, other = oracle_mod.lttb_step(y, n_out, k, A, j, x=x)
+                t1 = (XA - C[0]) * (Fraction(float(Y[j])) - YA)
+                t2 = (XA - Fraction(float(X[j]))) * (C[1] - YA)
+                exact = abs(t1 - t2)
+                assert abs(Fraction(other) - exact) <= Fraction(8, 2**53) * (abs(t1) + abs(t2)) + \
+                    Fraction(1, 2**1070), (trial, k, j)
+                areas.append(other)
+                assert pick == int(walk[k + 1])
+                if j == pick:
+                    assert other == best
+            assert best == max(areas) and areas.index(best) == pick - b[k]
+
+
 # ------------------------------------------------------------ MinMaxLTTB
 
 
