@@ -45,6 +45,8 @@ def _load():
         lib.oracle_lttb_area2.restype = ctypes.c_double
         lib.oracle_window.argtypes = [vp, i32, i64, i64, i64, _I64P, _I64P]
         lib.oracle_everynth.argtypes = [i64, i64, _I64P, _I64P]
+        lib.oracle_binned_parallel.argtypes = [vp, i32, vp, i32, i64, i64, i32, i32, _I64P, _I64P]
+        lib.oracle_binned_parallel.restype = ctypes.c_int
         for f in (lib.oracle_argminmax, lib.oracle_edges_nox, lib.oracle_edges_x, lib.oracle_minmax,
                   lib.oracle_m4, lib.oracle_lttb, lib.oracle_minmaxlttb,
                   lib.oracle_minmaxlttb_candidates, lib.oracle_lttb_centres, lib.oracle_lttb_step,
@@ -131,6 +133,22 @@ def nan_minmax(y, n_out, x=None):
 def nan_m4(y, n_out, x=None):
     """NaN-aware M4: NaN skipped in the argmin/argmax; first and last kept."""
     return _run(_load().oracle_nan_m4, y, n_out, x, max(n_out, len(y) if len(y) <= n_out else 0))
+
+
+def binned_parallel(algo, y, n_out, x=None, threads=1):
+    """MinMax or M4 (algo) with the bins split over `threads` host threads
+    (the CPU baseline's all-cores mode); the same result as minmax / m4."""
+    if algo not in ("minmax", "m4"):
+        raise ValueError(algo)
+    y, yp, yd = _arr(y)
+    x, xp, xd = _x(x)
+    cap = max(n_out, len(y) if len(y) <= n_out else 0)
+    out = np.empty(max(cap, 1), np.int64)
+    cnt = ctypes.c_int64()
+    rc = _load().oracle_binned_parallel(xp, xd, yp, yd, len(y), n_out, 1 if algo == "m4" else 0, int(threads),
+                                        _i64(out), ctypes.byref(cnt))
+    _check(rc, "binned_parallel")
+    return out[: cnt.value].copy()
 
 
 def lttb(y, n_out, x=None):

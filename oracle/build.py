@@ -16,7 +16,7 @@ def build(force: bool = True) -> str:
         return LIB
     tmp = LIB + ".tmp"
     subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
-                           "-Wall", "-Wextra", "-o", tmp, SRC, "-lm"])
+                           "-Wall", "-Wextra", "-pthread", "-o", tmp, SRC, "-lm"])
     os.replace(tmp, LIB)
     return LIB
 

@@ -32,6 +32,7 @@
  * argument; indices are int64.
  */
 #include <math.h>
+#include <pthread.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -301,6 +302,122 @@ int oracle_m4(const void *x, int xdt, const void *y, int ydt, int64_t n,
   free(edges);
   *count = m;
   return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Bin-parallel driver (CPU baseline only: Sec. 2.2 runs bins on all    */
+/* cores).  The same per-bin scalar loop as oracle_minmax / oracle_m4,  */
+/* with the bins split into contiguous ranges, one per thread; the      */
+/* result is identical because bins are independent.                   */
+/* ------------------------------------------------------------------ */
+
+/* First index in [0, n) whose x is >= E (integer x, exact). */
+static int64_t lower_bound_int(const void *x, int xdt, int64_t n, i128 E) {
+  int64_t lo = 0, hi = n;
+  while (lo < hi) {
+    int64_t mid = lo + (hi - lo) / 2;
+    if (int_x(x, xdt, mid) < E) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+/* First index in [0, n) whose (double)x is >= E (float x). */
+static int64_t lower_bound_flt(const void *x, int xdt, int64_t n, double E) {
+  int64_t lo = 0, hi = n;
+  while (lo < hi) {
+    int64_t mid = lo + (hi - lo) / 2;
+    if (load(x, xdt, mid).f < E) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+typedef struct {
+  const void *x; int xdt; const void *y; int ydt; int64_t n, nb; int m4;
+  int64_t b0, b1;
+  int64_t *edges, *sel, *cnt;
+} par_job;
+
+/* Edge b as oracle_edges_x / oracle_edges_nox define it (the first index at
+ * or above the edge value), found by bisection instead of the sweep. */
+static int64_t par_edge(const par_job *J, int64_t b) {
+  if (!J->x) {
+    i128 num = (i128)b * (i128)(J->n - 1);
+    i128 q = num / J->nb;
+    if (q * J->nb < num) q += 1;
+    return (int64_t)q;
+  }
+  if (dtype_class(J->xdt) != CLS_FLOAT) {
+    i128 x0 = int_x(J->x, J->xdt, 0), R = int_x(J->x, J->xdt, J->n - 1) - x0;
+    return lower_bound_int(J->x, J->xdt, J->n, int_edge_value(x0, R, b, J->nb));
+  }
+  double x0 = load(J->x, J->xdt, 0).f, R = load(J->x, J->xdt, J->n - 1).f - x0;
+  return lower_bound_flt(J->x, J->xdt, J->n, x0 + ((double)b * R) / (double)J->nb);
+}
+
+static void *par_edges(void *arg) {
+  par_job *J = (par_job *)arg;
+  for (int64_t b = J->b0; b < J->b1; b++) J->edges[b] = par_edge(J, b);
+  return NULL;
+}
+
+static void *par_bins(void *arg) {
+  par_job *J = (par_job *)arg;
+  for (int64_t b = J->b0; b < J->b1; b++) {
+    int64_t lo = J->edges[b], hi = J->edges[b + 1];
+    J->cnt[b] = 0;
+    if (lo >= hi) continue;
+    int64_t v[4];
+    int k = 0;
+    if (J->m4) v[k++] = lo;
+    oracle_argminmax(J->y, J->ydt, lo, hi, &v[k], &v[k + 1]);
+    k += 2;
+    if (J->m4) v[k++] = hi - 1;
+    J->cnt[b] = emit_sorted_distinct(v, k, J->sel + 4 * b);
+  }
+  return NULL;
+}
+
+/* MinMax (m4 = 0) or M4 (m4 = 1) over `threads` threads; same arguments and
+ * result as oracle_minmax / oracle_m4. */
+int oracle_binned_parallel(const void *x, int xdt, const void *y, int ydt, int64_t n, int64_t n_out, int m4,
+                           int threads, int64_t *out, int64_t *count) {
+  if (!y || !out || !count || !dtype_valid(ydt) || n < 0 || threads < 1 || threads > 1024) return -1;
+  const int64_t per = m4 ? 4 : 2;
+  if (n_out < per || n_out % per) return -1;
+  if (x && (xdt == OR_I8 || xdt == OR_I16 || xdt == OR_U8 || xdt == OR_U16 || xdt == OR_F16 ||
+            !dtype_valid(xdt)))
+    return -2;
+  if (n <= n_out) { *count = emit_all(n, out); return 0; }
+  const int64_t nb = n_out / per;
+  int64_t *edges = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nb + 1));
+  int64_t *sel = (int64_t *)malloc(sizeof(int64_t) * 4 * (size_t)nb);
+  int64_t *cnt = (int64_t *)malloc(sizeof(int64_t) * (size_t)nb);
+  par_job *jobs = (par_job *)malloc(sizeof(par_job) * (size_t)threads);
+  pthread_t *tid = (pthread_t *)malloc(sizeof(pthread_t) * (size_t)threads);
+  int rc = 0;
+  if (!edges || !sel || !cnt || !jobs || !tid) { rc = -3; goto done; }
+  edges[nb] = n;
+  for (int phase = 0; phase < 2; phase++) {
+    int started = 0;
+    for (int t = 0; t < threads; t++) {
+      par_job *J = &jobs[t];
+      J->x = x; J->xdt = xdt; J->y = y; J->ydt = ydt; J->n = n; J->nb = nb; J->m4 = m4;
+      J->b0 = (int64_t)(((i128)nb * t) / threads);
+      J->b1 = (int64_t)(((i128)nb * (t + 1)) / threads);
+      J->edges = edges; J->sel = sel; J->cnt = cnt;
+      if (pthread_create(&tid[t], NULL, phase == 0 ? par_edges : par_bins, J) != 0) { rc = -3; break; }
+      started++;
+    }
+    for (int t = 0; t < started; t++) pthread_join(tid[t], NULL);
+    if (rc) goto done;
+  }
+  int64_t m = 0;
+  for (int64_t b = 0; b < nb; b++)
+    for (int64_t j = 0; j < cnt[b]; j++) out[m++] = sel[4 * b + j];
+  *count = m;
+done:
+  free(edges); free(sel); free(cnt); free(jobs); free(tid);
+  return rc;
 }
 
 /* ------------------------------------------------------------------ */

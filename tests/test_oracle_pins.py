@@ -580,3 +580,28 @@ def test_golden_hand_worked_examples(oracle_mod):
         args = (y, c["n_out"]) + ((c["ratio"],) if c["algo"] == "minmaxlttb" else ())
         got = fn(*args, x=x)
         assert got.tolist() == c["expected"], (c["name"], got.tolist())
+
+
+# ------------------------------------------------------------ CPU baseline driver
+
+
+@pytest.mark.parametrize("algo", ["minmax", "m4"])
+def test_bin_parallel_driver_equals_serial(oracle_mod, algo):
+    """The all-cores CPU baseline splits the bins over threads and finds each
+    edge by bisection; it must select exactly what the serial scan does, with
+    and without x (integer with gaps and duplicates, float, unsigned), for
+    more threads than bins too."""
+    rng = np.random.default_rng(90)
+    for trial in range(12):
+        n = int(rng.integers(1, 30_000))
+        dt = ALL_DTYPES[trial % len(ALL_DTYPES)]
+        y = S.walk(n, dt, seed=trial)
+        xs = [None, np.maximum.accumulate(S.timestamps(n, 50, seed=trial) * (1 + (np.arange(n) > n // 2) * 40)),
+              np.sort(rng.random(n) * 1e3), S.timestamps(n, 9, seed=trial + 1).astype(np.uint64)]
+        xs[1][n // 3: n // 3 + 7] = xs[1][n // 3]
+        for x in xs:
+            for n_out in (4, 100, 4 * int(rng.integers(1, 3000))):
+                exp = getattr(oracle_mod, algo)(y, n_out, x=x)
+                for th in (1, 3, 16, 64):
+                    got = oracle_mod.binned_parallel(algo, y, n_out, x=x, threads=th)
+                    assert np.array_equal(got, exp), (trial, n, n_out, th)
