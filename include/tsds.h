@@ -59,7 +59,9 @@ enum {
   TS_ERR_NULL = -3,       /* required pointer is NULL, or x/x_dtype mismatch */
   TS_ERR_WORKSPACE = -4,  /* ws_bytes smaller than required, or ws misaligned */
   TS_ERR_HIP = -5,        /* a HIP runtime call or kernel launch failed */
-  TS_ERR_ALIGN = -6       /* an element pointer is not aligned to its size */
+  TS_ERR_ALIGN = -6,      /* an element pointer is not aligned to its size */
+  TS_ERR_CANCELLED = -7,  /* serving: the request was cancelled before it ran */
+  TS_ERR_TIMEOUT = -8     /* serving: the request waited longer than the server's timeout */
 };
 
 /* Algorithms. */
@@ -261,6 +263,8 @@ typedef struct {
                             ts_window + ts_minmaxlttb on one stream (baseline) */
   size_t arena_bytes;    /* device workspace per stream (0: max_batch worst-case requests);
                             raised to at least one worst-case request */
+  double timeout_s;      /* a request still pending this many seconds after submission is
+                            dropped with status TS_ERR_TIMEOUT (0: never) */
 } ts_server_config;
 
 /* One finished request.  Its indices (into the full series, strictly
@@ -268,7 +272,8 @@ typedef struct {
 typedef struct {
   int64_t id;
   int32_t series;
-  int32_t status;       /* TS_OK or the error of the batch it ran in */
+  int32_t status;       /* TS_OK, the error of the batch it ran in, or TS_ERR_CANCELLED /
+                           TS_ERR_TIMEOUT for a request that never ran (count 0) */
   int64_t count;
   int64_t offset;
   int64_t i0, i1;       /* the request's window [i0, i1) */
@@ -291,12 +296,19 @@ typedef struct ts_server ts_server;
  * their windows on the device, runs them as one batch (ts_batch_run's
  * kernels) and copies the results back; batches on different streams overlap
  * on the GPU, and requests that arrive meanwhile join the next free stream.
- * Every result equals ts_minmaxlttb on its window alone.  Allocates the
+ * A batch of one request runs the single-series kernels.  Every result
+ * equals ts_minmaxlttb on its window alone.  Allocates the
  * arenas and pinned buffers here; ts_server_free releases them. */
 int ts_server_create(const ts_series *series, int32_t n_series, const ts_server_config *cfg, ts_server **server);
 
 /* Queues a request; *req_id receives its id.  Thread-safe. */
 int ts_server_submit(ts_server *server, int32_t series, int64_t xa, int64_t xb, int64_t n_out, int64_t *req_id);
+
+/* Cancels a request that is still pending (not yet admitted to a stream):
+ * it comes back from ts_server_poll with status TS_ERR_CANCELLED and no
+ * indices.  TS_ERR_ARG if the request is unknown, already running or
+ * finished (a running batch always completes).  Thread-safe. */
+int ts_server_cancel(ts_server *server, int64_t req_id);
 
 /* Moves up to max_results finished requests out of the server: metadata to
  * res[], indices to the host buffer idx (capacity idx_cap); *n_results =

@@ -27,7 +27,7 @@ _F64P = ctypes.POINTER(ctypes.c_double)
 def _load():
     global _lib
     if _lib is None:
-        path = _build.build(force=False)
+        path = _build.build(force=False, sanitize=_build.sanitize_requested())
         lib = ctypes.CDLL(path)
         vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
         lib.oracle_argminmax.argtypes = [vp, i32, i64, i64, _I64P, _I64P]

@@ -10,7 +10,10 @@ import os
 
 import torch
 
-LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libtsds.so")
+# TSDS_SANITIZE=1 selects the build with ASan/UBSan on the host code (CPU
+# test runs; needs the sanitizer runtime preloaded)
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                        "libtsds_san.so" if os.environ.get("TSDS_SANITIZE", "") == "1" else "libtsds.so")
 
 TS_NONE = -1
 DTYPE_CODES = {
@@ -20,7 +23,7 @@ DTYPE_CODES = {
 }
 ALGO = {"minmax": 0, "m4": 1, "lttb": 2, "minmaxlttb": 3, "nan_minmax": 4, "nan_m4": 5}
 ERRORS = {-1: "TS_ERR_ARG", -2: "TS_ERR_DTYPE", -3: "TS_ERR_NULL", -4: "TS_ERR_WORKSPACE",
-          -5: "TS_ERR_HIP", -6: "TS_ERR_ALIGN"}
+          -5: "TS_ERR_HIP", -6: "TS_ERR_ALIGN", -7: "TS_ERR_CANCELLED", -8: "TS_ERR_TIMEOUT"}
 
 
 class TsSeries(ctypes.Structure):

@@ -17,9 +17,6 @@
 
 namespace tsds {
 
-int api_fail(int code, const char *msg);
-int api_check_series(const ts_series *s);
-int api_check_nout(int algo, int64_t n_out, int64_t ratio);
 size_t lttb_group_count(int64_t n_out);
 
 static size_t al256(size_t v) { return (v + 255) & ~(size_t)255; }

@@ -248,4 +248,10 @@ hipError_t launch_everynth(int64_t k, int64_t m, int64_t *out, int64_t *count, h
 hipError_t launch_gather(const void *x, int xs, const void *y, int ys, int64_t n, const int64_t *idx,
                          const int64_t *count, int64_t cap, void *xo, void *yo, hipStream_t st);
 
+// Host-side argument checks and the thread-local error message of the C ABI
+// (api.cpp), shared by the batched, served and allocation-free entry points.
+int api_fail(int code, const char *msg);
+int api_check_series(const ts_series *s);
+int api_check_nout(int algo, int64_t n_out, int64_t ratio);
+
 }  // namespace tsds

@@ -17,9 +17,16 @@
 // as a slot is free, so several batches overlap on the device (continuous
 // batching).  Every request's arithmetic is the same as a single
 // ts_minmaxlttb call on its window, whatever batch it lands in.
+// A batch of one request runs the single-series kernels (ts_minmaxlttb on its
+// window), which take fewer launches than the batched chain; larger batches
+// run as one batch.
 // Plain mode (cfg.plain = 1) runs each request alone, in arrival order, with
 // the single-series ts_window + ts_minmaxlttb calls: the comparison baseline.
+// Requests still pending can be cancelled (ts_server_cancel) and expire after
+// cfg.timeout_s; both come back from poll() with an error status and no
+// indices.  The scheduler's phases are marked as roctx ranges for profilers.
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
 #include <atomic>
@@ -34,11 +41,6 @@
 #include "batch_host.hpp"
 #include "internal.hpp"
 #include "tsds.h"
-
-namespace tsds {
-int api_fail(int code, const char *msg);
-int api_check_series(const ts_series *s);
-}  // namespace tsds
 
 using namespace tsds;
 
@@ -97,7 +99,7 @@ struct ts_server {
   std::thread worker;
   bool stop = false;
   int64_t next_id = 0;
-  int64_t batches = 0, max_batch_seen = 0, requests_done = 0;
+  int64_t batches = 0, max_batch_seen = 0, requests_done = 0, requests_dropped = 0;
   int device = 0;
   int error = 0;
   size_t ws_per_request_max = 0;
@@ -207,7 +209,7 @@ int run_batch(ts_server *sv, Slot &sl) {
   sl.t_run = now_s();
   const int nb = (int)sl.batch.size();
   const int64_t mo = sv->cfg.max_nout;
-  if (sv->cfg.plain) {
+  if (sv->cfg.plain || nb == 1) {
     for (int i = 0; i < nb; i++) {
       const ts_series s = window_series(sv, sl, i);
       int rc = ts_minmaxlttb(&s, sl.batch[i].n_out, sv->cfg.minmax_ratio, sl.d_out + i * mo, sl.d_counts + i, sl.ws,
@@ -294,22 +296,52 @@ void fail_batch(ts_server *sv, Slot &sl, int rc) {
   sl.state = FREE;
 }
 
+// A request that never ran: its result carries `status` and no indices.
+// Caller holds sv->mu.
+void drop_request(ts_server *sv, const Req &q, int status) {
+  Res r;
+  r.id = q.id;
+  r.series = q.series;
+  r.status = status;
+  r.i0 = r.i1 = 0;
+  r.t_submit = q.t_submit;
+  r.t_done = now_s();
+  r.t_admit = r.t_run = 0.0;
+  r.batch = 0;
+  sv->done.push_back(std::move(r));
+  sv->requests_dropped++;
+}
+
 void worker(ts_server *sv) {
   (void)hipSetDevice(sv->device);
   for (;;) {
     bool progressed = false;
     for (Slot &sl : sv->slots) {
       if (sl.state == RESOLVING && hipEventQuery(sl.ev_ranges) == hipSuccess) {
+        roctxRangePushA("tsds.serve.run");
         int rc = run_batch(sv, sl);
         if (rc) fail_batch(sv, sl, rc);
+        roctxRangePop();
         progressed = true;
       } else if (sl.state == RUNNING && hipEventQuery(sl.ev_done) == hipSuccess) {
+        roctxRangePushA("tsds.serve.finish");
         finish_batch(sv, sl);
+        roctxRangePop();
         progressed = true;
       }
     }
     {
       std::unique_lock<std::mutex> lk(sv->mu);
+      // expiry: pending requests are in submission order, so the expired
+      // ones are at the front
+      if (sv->cfg.timeout_s > 0.0) {
+        const double t = now_s();
+        while (!sv->pending.empty() && t - sv->pending.front().t_submit > sv->cfg.timeout_s) {
+          drop_request(sv, sv->pending.front(), TS_ERR_TIMEOUT);
+          sv->pending.pop_front();
+          progressed = true;
+        }
+      }
       bool busy = false;
       for (Slot &sl : sv->slots) busy |= sl.state != FREE;
       if (sv->stop && sv->pending.empty() && !busy) break;
@@ -328,8 +360,10 @@ void worker(ts_server *sv) {
           if (sv->cfg.plain) break;
         }
         lk.unlock();
+        roctxRangePushA("tsds.serve.admit");
         int rc = start_batch(sv, sl);
         if (rc) fail_batch(sv, sl, rc);
+        roctxRangePop();
         lk.lock();
         progressed = true;
       }
@@ -361,6 +395,7 @@ int ts_server_create(const ts_series *series, int32_t n_series, const ts_server_
   if (cfg->max_batch < 1 || cfg->max_batch > kMaxWindows) return api_fail(TS_ERR_ARG, "max_batch must be 1..32");
   if (cfg->max_nout < 3 || cfg->minmax_ratio < 1 || cfg->minmax_ratio > 30)
     return api_fail(TS_ERR_ARG, "bad max_nout / minmax_ratio");
+  if (!(cfg->timeout_s >= 0.0)) return api_fail(TS_ERR_ARG, "timeout_s must be >= 0");
   ts_server *sv = new ts_server();
   sv->cfg = *cfg;
   if (sv->cfg.plain) {
@@ -433,6 +468,18 @@ int ts_server_submit(ts_server *sv, int32_t series, int64_t xa, int64_t xb, int6
   sv->cv.notify_one();
   if (req_id) *req_id = q.id;
   return TS_OK;
+}
+
+int ts_server_cancel(ts_server *sv, int64_t req_id) {
+  if (!sv) return api_fail(TS_ERR_NULL, "server is NULL");
+  std::lock_guard<std::mutex> g(sv->mu);
+  for (auto it = sv->pending.begin(); it != sv->pending.end(); ++it) {
+    if (it->id != req_id) continue;
+    drop_request(sv, *it, TS_ERR_CANCELLED);
+    sv->pending.erase(it);
+    return TS_OK;
+  }
+  return api_fail(TS_ERR_ARG, "request is not pending (unknown, already admitted, or finished)");
 }
 
 int ts_server_poll(ts_server *sv, ts_result *res, int32_t max_results, int64_t *idx, int64_t idx_cap,

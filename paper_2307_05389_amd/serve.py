@@ -3,6 +3,7 @@ in HBM, continuously batched by libtsds's scheduler thread (marshalling only).
 
     srv = Server([(x0, y0), (x1, y1)], n_streams=4, max_batch=32)
     rid = srv.submit(series=0, xa=1000, xb=90000, n_out=2000)
+    srv.cancel(rid)        # only while it is still pending
     for r in srv.poll():   # dicts with id, indices (numpy), t_submit, t_done ...
         ...
     srv.close()
@@ -16,7 +17,8 @@ from . import _lib as L
 
 class TsServerConfig(ctypes.Structure):
     _fields_ = [("n_streams", ctypes.c_int32), ("max_batch", ctypes.c_int32), ("max_nout", ctypes.c_int64),
-                ("minmax_ratio", ctypes.c_int64), ("plain", ctypes.c_int32), ("arena_bytes", ctypes.c_size_t)]
+                ("minmax_ratio", ctypes.c_int64), ("plain", ctypes.c_int32), ("arena_bytes", ctypes.c_size_t),
+                ("timeout_s", ctypes.c_double)]
 
 
 class TsResult(ctypes.Structure):
@@ -41,6 +43,8 @@ def _setup(lib):
     lib.ts_server_stats.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64),
                                     ctypes.POINTER(i64)]
     lib.ts_server_stats.restype = ctypes.c_int
+    lib.ts_server_cancel.argtypes = [vp, i64]
+    lib.ts_server_cancel.restype = ctypes.c_int
     lib.ts_server_now.argtypes = []
     lib.ts_server_now.restype = ctypes.c_double
     lib.ts_server_free.argtypes = [vp]
@@ -50,14 +54,15 @@ def _setup(lib):
 
 class Server:
     def __init__(self, series, n_streams=4, max_batch=32, max_nout=4000, minmax_ratio=4, plain=False,
-                 arena_bytes=0):
+                 arena_bytes=0, timeout_s=0.0):
         self.lib = L.lib()
         _setup(self.lib)
         self._keep = list(series)
         arr = (L.TsSeries * len(series))()
         for i, (x, y) in enumerate(series):
             arr[i] = L.series(y, x)
-        cfg = TsServerConfig(n_streams, max_batch, max_nout, minmax_ratio, 1 if plain else 0, arena_bytes)
+        cfg = TsServerConfig(n_streams, max_batch, max_nout, minmax_ratio, 1 if plain else 0, arena_bytes,
+                             float(timeout_s))
         h = ctypes.c_void_p()
         L.check(self.lib.ts_server_create(arr, len(series), ctypes.byref(cfg), ctypes.byref(h)))
         self.h = h
@@ -73,6 +78,16 @@ class Server:
         rid = ctypes.c_int64()
         L.check(self.lib.ts_server_submit(self.h, int(series), int(xa), int(xb), int(n_out), ctypes.byref(rid)))
         return rid.value
+
+    def cancel(self, rid):
+        """Cancel a request that is still pending: True if it was (its result
+        then comes back with status TS_ERR_CANCELLED), False if it is already
+        running or finished."""
+        rc = self.lib.ts_server_cancel(self.h, int(rid))
+        if rc == -1:
+            return False
+        L.check(rc)
+        return True
 
     def poll(self):
         out = []

@@ -94,3 +94,70 @@ def test_server_rejects_bad_requests(resident):
     with pytest.raises(ts.TsArgError):
         srv.submit(3, 0, 10, 100)         # no such series
     srv.close()
+
+
+def test_cancel_and_timeout_leave_the_rest_exact(resident, oracle_mod):
+    """Cancelled and expired requests come back with their status and no
+    indices; every other request of the same burst still equals the oracle on
+    its window."""
+    import paper_2307_05389_amd as ts
+    series, dev = resident
+    reqs = requests(series, 120, seed=5)
+    # one stream, one request per batch: most of the burst waits in the queue
+    srv = ts.Server(dev, n_streams=1, max_batch=1, max_nout=1000, minmax_ratio=4)
+    ids = [srv.submit(*q) for q in reqs]
+    cancelled = {rid for rid in ids[10::3] if srv.cancel(rid)}
+    assert len(cancelled) > 10
+    assert not srv.cancel(10**9)                       # unknown id
+    got = collect(srv, len(ids))
+    srv.close()
+    say(f"[serve] cancelled {len(cancelled)} of {len(ids)}")
+    assert len(got) == len(ids)
+    for k, (rid, q) in enumerate(zip(ids, reqs)):
+        r = got[rid]
+        if rid in cancelled:
+            assert r["status"] == -7 and len(r["indices"]) == 0
+            continue
+        assert r["status"] == 0, (k, r["status"])
+        s, xa, xb, n_out = q
+        x, y = series[s]
+        i0, i1 = oracle_mod.window(x, xa, xb)
+        exp = i0 + oracle_mod.minmaxlttb(y[i0:i1], n_out, 4, x=x[i0:i1])
+        assert np.array_equal(r["indices"], exp), k
+    # a 1 ms timeout on a burst that takes several: the tail expires
+    srv = ts.Server(dev, n_streams=1, max_batch=1, max_nout=1000, minmax_ratio=4, timeout_s=0.001)
+    ids = [srv.submit(*q) for q in reqs]
+    got = collect(srv, len(ids))
+    srv.close()
+    status = [got[rid]["status"] for rid in ids]
+    say(f"[serve] timeout: {status.count(-8)} expired, {status.count(0)} served")
+    assert status.count(-8) > 0 and status.count(0) > 0 and set(status) <= {0, -8}
+    for k, (rid, q) in enumerate(zip(ids, reqs)):
+        r = got[rid]
+        if r["status"] != 0:
+            assert len(r["indices"]) == 0
+            continue
+        s, xa, xb, n_out = q
+        x, y = series[s]
+        i0, i1 = oracle_mod.window(x, xa, xb)
+        exp = i0 + oracle_mod.minmaxlttb(y[i0:i1], n_out, 4, x=x[i0:i1])
+        assert np.array_equal(r["indices"], exp), k
+
+
+def test_single_request_batches_equal_oracle(resident, oracle_mod):
+    """Requests that arrive one at a time run as batches of one (the
+    single-series kernels); their results equal the oracle too."""
+    import paper_2307_05389_amd as ts
+    series, dev = resident
+    reqs = requests(series, 40, seed=6)
+    srv = ts.Server(dev, n_streams=4, max_batch=32, max_nout=1000, minmax_ratio=4)
+    for k, q in enumerate(reqs):
+        rid = srv.submit(*q)
+        r = collect(srv, 1)[rid]
+        assert r["status"] == 0 and r["batch_size"] == 1
+        s, xa, xb, n_out = q
+        x, y = series[s]
+        i0, i1 = oracle_mod.window(x, xa, xb)
+        exp = i0 + oracle_mod.minmaxlttb(y[i0:i1], n_out, 4, x=x[i0:i1])
+        assert np.array_equal(r["indices"], exp), k
+    srv.close()
