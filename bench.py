@@ -83,27 +83,67 @@ def load_traffic(kernel, workload):
     return e.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(name, x, y, w, budget_s=12.0):
-    import oracle
-    fn = {"m4": oracle.m4, "minmax": oracle.minmax}.get(w["algo"])
-    times = []
+def cpu_share():
+    """Host cores this process may use, capped at 16 (the host CPU share of
+    one GPU on the benchmark machines)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _median_runs(fn, budget_s, max_runs=50):
+    times, res = [], None
     t_start = time.perf_counter()
-    res = None
-    while (len(times) < 3 or time.perf_counter() - t_start < budget_s) and len(times) < 50:
+    while (len(times) < 3 or time.perf_counter() - t_start < budget_s) and len(times) < max_runs:
         t0 = time.perf_counter()
-        if w["algo"] == "minmaxlttb":
-            res = oracle.minmaxlttb(y, w["n_out"], 4, x=x)
-        else:
-            res = fn(y, w["n_out"], x=x)
+        res = fn()
         times.append(time.perf_counter() - t0)
-    med = float(np.median(times))
-    gbs = y.nbytes / med / 1e9
-    return {"value": round(gbs, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
-            "sample": f"the full workload ({len(y):,} points), {len(times)} single-thread runs, median "
-                      f"{med * 1e3:.1f} ms"}, res
+    return float(np.median(times)), len(times), res
 
 
-def bench_batched(seed=3, n_series=512, reps=10, check_oracle=True):
+def cpu_baseline(name, x, y, w, budget_s=8.0):
+    """The oracle on the host: single-threaded, and (MinMax / M4) with its bins
+    split over every core of the host share (the paper's parallel=True mode;
+    the same per-bin loop, identical output)."""
+    import oracle
+    if w["algo"] == "minmaxlttb":
+        serial = lambda: oracle.minmaxlttb(y, w["n_out"], 4, x=x)
+    else:
+        serial = lambda: getattr(oracle, w["algo"])(y, w["n_out"], x=x)
+    med1, runs1, res = _median_runs(serial, budget_s)
+    single = {"value": round(y.nbytes / med1 / 1e9, 3), "unit": "GB/s", "cores": 1,
+              "median_ms": round(med1 * 1e3, 2), "runs": runs1}
+    out = {"value": single["value"], "unit": "GB/s", "cores": 1, "kind": "oracle",
+           "sample": f"the full workload ({len(y):,} points), {runs1} single-thread runs, median "
+                     f"{med1 * 1e3:.1f} ms", "cpu_model": cpu_model(), "host_cpus_visible": os.cpu_count(),
+           "single_core": single}
+    if w["algo"] in ("minmax", "m4"):
+        T = cpu_share()
+        medT, runsT, resT = _median_runs(
+            lambda: oracle.binned_parallel(w["algo"], y, w["n_out"], x=x, threads=T), budget_s / 2)
+        if not np.array_equal(resT, res):
+            raise RuntimeError("bin-parallel oracle differs from the serial oracle")
+        out.update({"value": round(y.nbytes / medT / 1e9, 3), "cores": T,
+                    "sample": f"the full workload ({len(y):,} points), bins split over {T} threads, {runsT} runs, "
+                              f"median {medT * 1e3:.1f} ms; single thread: {runs1} runs, median "
+                              f"{med1 * 1e3:.1f} ms"})
+    return out, res
+
+
+def bench_batched(seed=3, n_series=512, reps=10, check_oracle=True, tuning=None, plain=True):
     """Batched vs plain on the mixed batch: 512 series, lengths log-uniform in
     1e4..2e7, dtypes f32/f16/i16/u8, MinMax / M4, n_out 500..4000.  With
     check_oracle (part of the CPU-baseline leg), a sample of tasks is also
@@ -117,7 +157,15 @@ def bench_batched(seed=3, n_series=512, reps=10, check_oracle=True):
     total_bytes = sum(y.numel() * y.element_size() for y in ys)
     tasks = [dict(algo=s["algo"], y=y, n_out=s["n_out"]) for s, y in zip(specs, ys)]
     b = tsds.Batch(tasks)
-    tune = b.autotune()
+    if tuning is None:
+        tune = b.autotune()
+    else:   # a fixed tuning (profiling runs: no autotune candidates in the trace)
+        b.set_tuning(*tuning)
+        tune = b.tuning()
+    group_bytes = {}
+    for sp, y in zip(specs, ys):
+        k = str(sp["dtype"])
+        group_bytes[k] = group_bytes.get(k, 0) + y.numel() * y.element_size()
     st = torch.cuda.current_stream()
     b.run(graph=True)
     torch.cuda.synchronize()
@@ -129,6 +177,11 @@ def bench_batched(seed=3, n_series=512, reps=10, check_oracle=True):
     torch.cuda.synchronize()
     t_batch = e0.elapsed_time(e1) / reps
     batched = [r.clone() for r in b.results()]
+    if not plain:
+        b.close()
+        return {"batched_ms": round(t_batch, 4), "batched_GBps": round(total_bytes / t_batch / 1e6, 1),
+                "group_bytes": group_bytes, "replays": reps + 1,
+                "tuning": {"chunk_bytes": tune[0], "small_bin": tune[1], "grid_blocks": tune[2]}}
     # plain: one single-series call per task on one stream (own outputs, one
     # shared workspace), eager and replayed from a torch-captured graph
     outs = [torch.empty(s["n_out"], dtype=torch.int64, device=y.device) for s, y in zip(specs, ys)]
@@ -185,7 +238,7 @@ def bench_batched(seed=3, n_series=512, reps=10, check_oracle=True):
         "plain_graph_ms": round(t_plain_graph, 4),
         "speedup_vs_plain_eager": round(t_plain_eager / t_batch, 2),
         "speedup_vs_plain_graph": round(t_plain_graph / t_batch, 2),
-        "identical_to_plain": identical, "oracle_sample_bit_exact": ok,
+        "identical_to_plain": identical, "oracle_sample_bit_exact": ok, "group_bytes": group_bytes,
         "tuning": {"chunk_bytes": tune[0], "small_bin": tune[1], "grid_blocks": tune[2]},
     }
 
@@ -208,9 +261,8 @@ def bench_served(full=False, n_series=64, n_points=200_000_000, check_oracle=Tru
     x_first = [int(x[0].item()) for x, _ in series]
     x_last = [int(x[-1].item()) for x, _ in series]
     resident_gb = sum(x.numel() * 8 + y.numel() * 4 for x, y in series) / 1e9
-    qps_list = [100.0, 1000.0, 5000.0, 20000.0] if full else [1000.0, 5000.0, 20000.0]
-    n_req = 10000 if full else 2000
-    n_warm = 500 if full else 200
+    qps_list = [100.0, 1000.0, 5000.0, 10000.0, 20000.0] if full else [1000.0, 5000.0, 10000.0, 20000.0]
+    n_req, n_warm = 10000, 500
 
     def run(srv, qps, seed):
         reqs = S.zoom_requests(n_req + n_warm, n_series, x_first, x_last, seed=seed, qps=qps)
@@ -257,25 +309,35 @@ def bench_served(full=False, n_series=64, n_points=200_000_000, check_oracle=Tru
                 "points_per_s": round(pts / (last - first), 1),
                 "mean_batch": round(float(np.mean(bs)), 2)}, by_k, reqs
 
+    p99_bound_ms = 1.0
     out = {"workload": f"{n_series} resident series x {n_points:,} float32 points + int64 timestamps "
                        f"({resident_gb:.1f} GB), MinMaxLTTB ratio 4, n_out 800..4000, {n_req} requests "
-                       f"(+{n_warm} warm-up) per rate", "served": [], "plain": []}
+                       f"(+{n_warm} warm-up) per rate, the same request trace for both modes",
+           "served": [], "plain": []}
+    # both modes on the same trace per rate; served and plain alternate so
+    # that neither sees a systematically warmer GPU
     srv = tsds.Server(series, n_streams=4, max_batch=32, max_nout=4000, minmax_ratio=4)
+    plain = tsds.Server(series, plain=True, max_nout=4000, minmax_ratio=4)
     served_first = None
+    identical = True
     for i, qps in enumerate(qps_list):
         log(f"[bench] served at {qps} QPS")
         stats, by_k, reqs = run(srv, qps, seed=4 + i)
         out["served"].append(stats)
+        log(f"[bench] plain FIFO at {qps} QPS")
+        pstats, pk, _ = run(plain, qps, seed=4 + i)
+        out["plain"].append(pstats)
+        identical &= all(np.array_equal(by_k[k]["indices"], pk[k]["indices"]) for k in by_k)
         if i == 0:
             served_first = (by_k, reqs)
     srv.close()
-    plain = tsds.Server(series, plain=True, max_nout=4000, minmax_ratio=4)
-    log(f"[bench] plain FIFO at {qps_list[0]} QPS")
-    stats, pk, _ = run(plain, qps_list[0], seed=4)
-    out["plain"].append(stats)
     plain.close()
     by_k, reqs = served_first
-    out["identical_served_vs_plain"] = all(np.array_equal(by_k[k]["indices"], pk[k]["indices"]) for k in by_k)
+    out["identical_served_vs_plain"] = bool(identical)
+    out["p99_bound_ms"] = p99_bound_ms
+    for mode in ("served", "plain"):
+        ok = [r["qps"] for r in out[mode] if r["p99_ms"] <= p99_bound_ms]
+        out[f"{mode}_max_qps_p99_within_bound"] = max(ok) if ok else None
     # oracle on a few requests (window copied to the host; CPU-baseline leg)
     ok = None
     if check_oracle:
@@ -294,6 +356,56 @@ def bench_served(full=False, n_series=64, n_points=200_000_000, check_oracle=Tru
     return out
 
 
+def _exact_bucket_sums(v, starts):
+    """Exact sums and exact sums of |v| of float32 values v over the buckets
+    [starts[k], starts[k+1]), as Python integers times 2^-149: every float32 is
+    an integer multiple of 2^-149, so the sums are grouped by exponent (the
+    per-exponent integer sums stay below 2^53 and are exact in float64) and
+    combined in Python integers."""
+    bits = np.ascontiguousarray(v, np.float32).view(np.uint32)
+    e = ((bits >> 23) & 0xFF).astype(np.int64)
+    mant = (bits & 0x7FFFFF).astype(np.int64) + np.where(e > 0, 1 << 23, 0)
+    shift = np.maximum(e - 1, 0)                    # value = mant * 2^(shift - 149)
+    sgn = np.where(bits >> 31, -1, 1)
+    bucket = np.repeat(np.arange(len(starts) - 1), np.diff(starts))
+    key = bucket * 256 + shift
+    sums = np.bincount(key, weights=(sgn * mant).astype(np.float64), minlength=256 * (len(starts) - 1))
+    abss = np.bincount(key, weights=mant.astype(np.float64), minlength=256 * (len(starts) - 1))
+    out, out_abs = [], []
+    for k in range(len(starts) - 1):
+        row, arow = sums[256 * k: 256 * k + 256], abss[256 * k: 256 * k + 256]
+        nz = np.nonzero(arow)[0]
+        out.append(sum(int(row[j]) << int(j) for j in nz))
+        out_abs.append(sum(int(arow[j]) << int(j) for j in nz))
+    return out, out_abs
+
+
+def lttb_mean_error(tsds, yd, y, n_out, sel=None):
+    """Largest error of the GPU's LTTB bucket centres (the FP64 means of the
+    next bucket) against the exact rational means, relative to the bucket's
+    mean |value| (= |mean| when the values share a sign).  float32 y, no x:
+    X is the index, whose means are exact (reported too)."""
+    from fractions import Fraction
+    import torch
+    seld = None if sel is None else torch.from_numpy(sel).to(yd.device)
+    cx, cy = tsds.lttb_centres(yd, n_out, sel=seld)
+    cx, cy = cx.cpu().numpy(), cy.cpu().numpy()
+    idx = np.arange(len(y), dtype=np.int64) if sel is None else sel
+    m, nb = len(idx), n_out - 2
+    b = np.array([1 + (k * (m - 2)) // nb for k in range(nb + 1)], np.int64)
+    vals = y if sel is None else y[sel]
+    sums, abss = _exact_bucket_sums(vals[b[1]: b[nb]], b[1: nb + 1] - b[1])
+    isum = np.add.reduceat(idx[b[1]: b[nb]], (b[1: nb] - b[1]))
+    worst_y = worst_x = 0.0
+    for k in range(nb - 1):
+        cnt = int(b[k + 2] - b[k + 1])
+        if abss[k]:
+            err = abs(Fraction(float(cy[k])) - Fraction(sums[k], cnt << 149)) / Fraction(abss[k], cnt << 149)
+            worst_y = max(worst_y, float(err))
+        worst_x = max(worst_x, float(abs(Fraction(float(cx[k])) - Fraction(int(isum[k]), cnt)) / Fraction(int(isum[k]), cnt)))
+    return max(worst_x, worst_y), worst_y
+
+
 def bench_configs(reps_small=200, reps_big=10, check_oracle=True):
     """The other configurations: MinMax at 1e6 (latency-bound), MinMaxLTTB at
     5e8 (preselection scan + candidate LTTB) and plain LTTB at 1e8 (the
@@ -302,6 +414,7 @@ def bench_configs(reps_small=200, reps_big=10, check_oracle=True):
     the CPU-baseline leg), checked against the oracle on the host."""
     import torch
     import paper_2307_05389_amd as tsds
+    from paper_2307_05389_amd import _lib as L
     import synthetic as S
     dev = torch.device("cuda:0")
     st = torch.cuda.current_stream(dev)
@@ -346,11 +459,42 @@ def bench_configs(reps_small=200, reps_big=10, check_oracle=True):
             import oracle
             ref = oracle.minmaxlttb(y, n_out, 4) if algo == "minmaxlttb" else getattr(oracle, algo)(y, n_out)
             parity = "bit-exact" if np.array_equal(got, ref) else "MISMATCH"
-        out.append({"algo": algo, "workload": desc, "n": int(y.size), "n_out": n_out, "ms": round(ms, 4),
-                    "GBps": round(y.nbytes / ms / 1e6, 1), "points_per_s": round(y.size / ms * 1e3, 1),
-                    "frac_of_hbm_peak": round(y.nbytes / ms / 1e6 / HBM_PEAK_GBS, 4),
-                    "parity_vs_oracle": parity,
-                    "paper_context": paper + "; 32-thread Xeon E5-2650 v2, other hardware"})
+        line = {"algo": algo, "workload": desc, "n": int(y.size), "n_out": n_out, "ms": round(ms, 4),
+                "GBps": round(y.nbytes / ms / 1e6, 1), "points_per_s": round(y.size / ms * 1e3, 1),
+                "frac_of_hbm_peak": round(y.nbytes / ms / 1e6 / HBM_PEAK_GBS, 4),
+                "parity_vs_oracle": parity,
+                "paper_context": paper + "; 32-thread Xeon E5-2650 v2, other hardware"}
+        if algo in ("lttb", "minmaxlttb"):
+            sel = None
+            if algo == "minmaxlttb":   # the candidates: first point, interior MinMax, last point
+                pre = tsds.minmax(yd[1:-1], n_out * 4).cpu().numpy() + 1
+                sel = np.concatenate([[0], pre, [y.size - 1]]).astype(np.int64)
+            err, err_y = lttb_mean_error(tsds, yd, y, n_out, sel)
+            line["max_mean_rel_err"] = err
+            line["mean_err_reference"] = "exact rational bucket means; error relative to the bucket's mean |value|"
+            # a walk identical to the oracle's uses no near-tie acceptance
+            line["near_ties"] = 0 if parity == "bit-exact" else None
+        out.append(line)
+        if algo == "minmaxlttb":
+            # the MinMax variant of the same 5e8-point series (n_out 2000: 1000 bins)
+            fn = lambda: tsds.downsample_into("minmax", yd, 2000, o, c, workspace=ws2, stream=st)
+            ws2 = torch.empty(max(tsds.workspace_bytes("minmax", yd, 2000), 256), dtype=torch.uint8, device=dev)
+            ms = timed(fn, reps * 2)
+            got = o[: int(c.item())].cpu().numpy()
+            parity = None
+            if check_oracle:
+                import oracle
+                ref = oracle.binned_parallel("minmax", y, 2000, threads=cpu_share())
+                parity = "bit-exact" if np.array_equal(got, ref) else "MISMATCH"
+            out.append({"algo": "minmax", "workload": "MinMax no x, float32 random walk with 5% constant runs, "
+                        "N=5e8, n_out=2000", "n": int(y.size), "n_out": 2000, "ms": round(ms, 4),
+                        "GBps": round(y.nbytes / ms / 1e6, 1), "points_per_s": round(y.size / ms * 1e3, 1),
+                        "frac_of_hbm_peak": round(y.nbytes / ms / 1e6 / HBM_PEAK_GBS, 4),
+                        "kernel": L.scan_config(yd.dtype, y.size, 1000)[2], "parity_vs_oracle": parity,
+                        "paper_context": "tsdownsample MinMax float32 N=1e9 parallel: 88.75 ms (45.1 GB/s); "
+                                         "32-thread Xeon E5-2650 v2, other hardware"})
+            log(f"[bench] config minmax 5e8: {ms:.3f} ms")
+            del ws2
         log(f"[bench] config {algo}: {ms:.3f} ms")
         del yd, ws, y
         torch.cuda.empty_cache()
@@ -362,7 +506,6 @@ def bench_configs(reps_small=200, reps_big=10, check_oracle=True):
     yd = torch.zeros(n, dtype=torch.float32, device=dev)
     o = torch.empty(2000, dtype=torch.int64, device=dev)
     c = torch.zeros(1, dtype=torch.int64, device=dev)
-    from paper_2307_05389_amd import _lib as L
     import ctypes
     s = L.series(yd)
     sp = ctypes.c_void_p(st.cuda_stream)
@@ -427,6 +570,65 @@ def bench_configs(reps_small=200, reps_big=10, check_oracle=True):
     return out
 
 
+def bench_dtypes(reps=10, check_oracle=True):
+    """MinMax and M4 over 1 GB of uniform random values in the narrow dtypes
+    of the paper's Table 1 (u8: 1e9 points; i16 and f16: 5e8 points), no x,
+    with 1,000 and 100,000 bins; timed with HIP events around the whole call
+    and (CPU-baseline leg) checked against the oracle."""
+    import torch
+    import paper_2307_05389_amd as tsds
+    from paper_2307_05389_amd import _lib as L
+    dev = torch.device("cuda:0")
+    st = torch.cuda.current_stream(dev)
+    g = torch.Generator(device=dev)
+    g.manual_seed(12)
+    lines = []
+    for name, n in (("uint8", 1_000_000_000), ("int16", 500_000_000), ("float16", 500_000_000)):
+        log(f"[bench] dtypes: {name} x {n:,}")
+        if name == "float16":
+            yd = torch.randn(n, generator=g, device=dev, dtype=torch.float32).to(torch.float16)
+        else:
+            tdt = getattr(torch, name)
+            info = torch.iinfo(tdt)
+            yd = torch.randint(info.min, info.max + 1, (n,), generator=g, device=dev, dtype=torch.int64).to(tdt)
+        yh = yd.cpu().numpy() if check_oracle else None
+        for algo in ("minmax", "m4"):
+            for bins in (1000, 100_000):
+                n_out = bins * (2 if algo == "minmax" else 4)
+                o = torch.empty(n_out, dtype=torch.int64, device=dev)
+                c = torch.zeros(1, dtype=torch.int64, device=dev)
+                ws = torch.empty(max(tsds.workspace_bytes(algo, yd, n_out), 256), dtype=torch.uint8, device=dev)
+                fn = lambda: tsds.downsample_into(algo, yd, n_out, o, c, workspace=ws, stream=st)
+                for _ in range(3):
+                    fn()
+                torch.cuda.synchronize()
+                ts_ = []
+                for _ in range(reps):
+                    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    a.record(st)
+                    fn()
+                    b.record(st)
+                    b.synchronize()
+                    ts_.append(a.elapsed_time(b))
+                ms = float(np.median(ts_))
+                parity = None
+                if check_oracle:
+                    import oracle
+                    ref = oracle.binned_parallel(algo, yh, n_out, threads=cpu_share())
+                    parity = "bit-exact" if np.array_equal(o[: int(c.item())].cpu().numpy(), ref) else "MISMATCH"
+                nbytes = n * yd.element_size()
+                lines.append({"algo": algo, "dtype": name, "n": n, "n_out": n_out, "bins": bins, "ms": round(ms, 4),
+                              "GBps": round(nbytes / ms / 1e6, 1), "frac_of_hbm_peak": round(nbytes / ms / 1e6 /
+                                                                                          HBM_PEAK_GBS, 4),
+                              "kernel": L.scan_config(yd.dtype, n, bins)[2], "parity_vs_oracle": parity})
+                log(f"[bench] dtypes: {algo} {name} {bins} bins: {ms:.4f} ms ({nbytes / ms / 1e6:.0f} GB/s)")
+                del ws
+        del yd, yh
+        torch.cuda.empty_cache()
+    return {"workload": "uniform random values (the paper's Table 1 input), no x, 1 GB per series",
+            "lines": lines}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -441,8 +643,11 @@ def main():
     ap.add_argument("--serve-full", action="store_true", help="served sweep at 100..20000 QPS, 10000 requests each")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain device copy of y (for counter calibration)")
-    ap.add_argument("--legs", default="configs,batched,served",
-                    help="comma list of the extra legs to run after the headline: configs, batched, served")
+    ap.add_argument("--batch-tuning", default=None,
+                    help="chunk_bytes,small_bin,grid_blocks for the batched leg instead of autotuning, and no "
+                         "plain comparison (for kernel traces of the batched replays alone)")
+    ap.add_argument("--legs", default="configs,dtypes,batched,served",
+                    help="comma list of the extra legs to run after the headline: configs, dtypes, batched, served")
     args = ap.parse_args()
     legs = set(x for x in args.legs.split(",") if x)
     if args.gpus != 1:
@@ -456,10 +661,18 @@ def main():
 
     w = WORKLOADS[args.workload]
     log(f"[bench] generating {args.workload} ({w['n']:,} points)")
-    x, y = make_inputs(args.workload)
     dev = torch.device("cuda:0")
-    yd = torch.from_numpy(y).to(dev)
-    xd = torch.from_numpy(x).to(dev) if x is not None else None
+    if args.workload == "m4x":
+        # generated on the GPU; host copies (for the oracle) are taken after
+        # the timed region
+        import synthetic as S
+        xd, yd = S.device_m4_with_x(w["n"], seed=1, device=dev)
+        x = y = None
+    else:
+        x, y = make_inputs(args.workload)
+        yd = torch.from_numpy(y).to(dev)
+        xd = torch.from_numpy(x).to(dev) if x is not None else None
+    y_nbytes = yd.numel() * yd.element_size()
     out = torch.empty(w["n_out"], dtype=torch.int64, device=dev)
     cnt = torch.zeros(1, dtype=torch.int64, device=dev)
     st = torch.cuda.current_stream(dev)
@@ -497,11 +710,14 @@ def main():
     L.check(lib.ts_profile_scan_events(None, None))
     ms_step = (t1 - t0) * 1e3 / args.steps
     scan_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
-    gbytes = y.nbytes / 1e9
+    gbytes = y_nbytes / 1e9
     value = gbytes / (ms_step / 1e3)
     achieved = gbytes / (scan_ms / 1e3)
     got = out[: int(cnt.item())].cpu().numpy()
     log(f"[bench] {ms_step:.4f} ms/step, scan kernel {scan_ms:.4f} ms ({achieved:.0f} GB/s)")
+    if y is None:
+        x = xd.cpu().numpy() if xd is not None else None
+        y = yd.cpu().numpy()
 
     nb = {"m4": w["n_out"] // 4, "minmax": w["n_out"] // 2, "minmaxlttb": w["n_out"] * 4 // 2}[w["algo"]]
     variant, chunk_bytes, kernel = L.scan_config(yd.dtype, w["n"] if w["algo"] != "minmaxlttb" else w["n"] - 2,
@@ -540,8 +756,12 @@ def main():
         chk = not args.no_cpu_baseline
         if "configs" in legs:
             res["other_configs"] = bench_configs(check_oracle=chk)
+        if "dtypes" in legs:
+            res["narrow_dtypes"] = bench_dtypes(check_oracle=chk)
+            torch.cuda.empty_cache()
         if "batched" in legs:
-            res["batched"] = bench_batched(check_oracle=chk)
+            bt = None if args.batch_tuning is None else tuple(int(v) for v in args.batch_tuning.split(","))
+            res["batched"] = bench_batched(check_oracle=chk and bt is None, tuning=bt, plain=bt is None)
             torch.cuda.empty_cache()
         if "served" in legs:
             res["served"] = bench_served(full=args.serve_full, check_oracle=chk)

@@ -191,6 +191,31 @@ def device_timestamps(n, seed, gap_max=100, device="cuda", chunk=1 << 26):
     return out
 
 
+def device_m4_with_x(n, seed=1, device="cuda", chunk=1 << 25):
+    """The M4-with-x workload generated on the GPU (torch Philox): int64
+    timestamps with gaps uniform in 1..1000, and float64 y = 3 sin(2 pi 7 t)
+    + 2 sin(2 pi 113 t + 0.5) + sin(2 pi 2029 t + 1.3) + N(0, 0.1) with
+    t = x / x[-1], plus a +-50 spike on 1% of the points.  The same
+    distributions as m4_with_x, other numbers."""
+    import torch
+    x = device_timestamps(n, seed, gap_max=1000, device=device)
+    g = torch.Generator(device=device)
+    g.manual_seed(seed + 104729)
+    y = torch.empty(n, dtype=torch.float64, device=device)
+    span = float(x[-1].item()) or 1.0
+    for s in range(0, n, chunk):
+        e = min(n, s + chunk)
+        t = x[s:e].to(torch.float64) / span
+        v = (3 * torch.sin(2 * math.pi * 7 * t) + 2 * torch.sin(2 * math.pi * 113 * t + 0.5)
+             + torch.sin(2 * math.pi * 2029 * t + 1.3))
+        v += 0.1 * torch.randn(e - s, generator=g, device=device, dtype=torch.float64)
+        spike = torch.rand(e - s, generator=g, device=device, dtype=torch.float64) < 0.01
+        sign = torch.where(torch.rand(e - s, generator=g, device=device, dtype=torch.float64) < 0.5, -50.0, 50.0)
+        y[s:e] = v + torch.where(spike, sign, torch.zeros_like(sign))
+        del t, v, spike, sign
+    return x, y
+
+
 def device_walk_cast(n, dtype, seed, device="cuda"):
     """Random walk generated on the GPU in float64 (torch Philox), then cast
     like cast_walk: floats round to nearest, integers are rounded and clipped
