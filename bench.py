@@ -406,7 +406,7 @@ def lttb_mean_error(tsds, yd, y, n_out, sel=None):
     return max(worst_x, worst_y), worst_y
 
 
-def bench_configs(reps_small=200, reps_big=10, check_oracle=True):
+def bench_configs(reps_small=200, reps_big=10, check_oracle=True, only=None):
     """The other configurations: MinMax at 1e6 (latency-bound), MinMaxLTTB at
     5e8 (preselection scan + candidate LTTB) and plain LTTB at 1e8 (the
     paper's Table 1 LTTB row, one workgroup walking the buckets), each timed
@@ -443,7 +443,10 @@ def bench_configs(reps_small=200, reps_big=10, check_oracle=True):
         ("lttb", "plain LTTB no x, float32 random walk, N=1e8, n_out=2000", lambda: S.walk(100_000_000, np.float32, seed=5),
          2000, reps_big, "tsdownsample LTTB float32 N=1e8 (sequential only): 173.72 ms (2.3 GB/s)"),
     ]
+    want = lambda name: only is None or name in only
     for algo, desc, gen, n_out, reps, paper in cases:
+        if not want(algo):
+            continue
         log(f"[bench] config {algo}: generating")
         y = gen()
         yd = torch.from_numpy(y).to(dev)
@@ -501,12 +504,27 @@ def bench_configs(reps_small=200, reps_big=10, check_oracle=True):
 
     # EveryNth over 1e8 points (reads no data: a launch plus n_out index writes)
     # and the fused gather of an M4 selection's (x, y) for drawing.
+    if not (want("everynth") or want("m4+gather") or want("nan_m4")):
+        return out
+    import ctypes
+    sp = ctypes.c_void_p(st.cuda_stream)
+    if want("everynth"):
+        out.append(_config_everynth(tsds, L, st, timed, reps_small, check_oracle))
+    if not (want("m4+gather") or want("nan_m4")):
+        return out
+    out += _config_m4_gather_nan(tsds, L, S, dev, st, sp, timed, reps_big, check_oracle)
+    return out
+
+
+def _config_everynth(tsds, L, st, timed, reps_small, check_oracle):
+    import ctypes
+    import torch
+    dev = torch.device("cuda:0")
     log("[bench] config everynth")
     n = 100_000_000
     yd = torch.zeros(n, dtype=torch.float32, device=dev)
     o = torch.empty(2000, dtype=torch.int64, device=dev)
     c = torch.zeros(1, dtype=torch.int64, device=dev)
-    import ctypes
     s = L.series(yd)
     sp = ctypes.c_void_p(st.cuda_stream)
     ms = timed(lambda: L.check(L.lib().ts_everynth(ctypes.byref(s), 2000, L._ptr(o), L._ptr(c), sp)), reps_small)
@@ -515,12 +533,18 @@ def bench_configs(reps_small=200, reps_big=10, check_oracle=True):
         import oracle
         parity = "bit-exact" if np.array_equal(o[: int(c.item())].cpu().numpy(), oracle.everynth(n, 2000)) \
             else "MISMATCH"
-    out.append({"algo": "everynth", "workload": "EveryNth, N=1e8, n_out=2000", "n": n, "n_out": 2000,
-                "ms": round(ms, 4), "parity_vs_oracle": parity,
-                "paper_context": "tsdownsample EveryNth: about 0.02 ms at every size; 32-thread Xeon E5-2650 v2, "
-                                 "other hardware"})
     log(f"[bench] config everynth: {ms:.4f} ms")
     del yd
+    return {"algo": "everynth", "workload": "EveryNth, N=1e8, n_out=2000", "n": n, "n_out": 2000,
+            "ms": round(ms, 4), "parity_vs_oracle": parity,
+            "paper_context": "tsdownsample EveryNth: about 0.02 ms at every size; 32-thread Xeon E5-2650 v2, "
+                             "other hardware"}
+
+
+def _config_m4_gather_nan(tsds, L, S, dev, st, sp, timed, reps_big, check_oracle):
+    import ctypes
+    import torch
+    out = []
     log("[bench] config m4+gather")
     n = 100_000_000
     yd = S.device_walk(n, seed=1, device=dev, dtype=torch.float64)
@@ -646,6 +670,9 @@ def main():
     ap.add_argument("--batch-tuning", default=None,
                     help="chunk_bytes,small_bin,grid_blocks for the batched leg instead of autotuning, and no "
                          "plain comparison (for kernel traces of the batched replays alone)")
+    ap.add_argument("--configs", default=None,
+                    help="comma list of the configs leg's entries to run (minmax, minmaxlttb, lttb, everynth, "
+                         "m4+gather, nan_m4; default all)")
     ap.add_argument("--legs", default="configs,dtypes,batched,served",
                     help="comma list of the extra legs to run after the headline: configs, dtypes, batched, served")
     args = ap.parse_args()
@@ -755,7 +782,8 @@ def main():
         torch.cuda.empty_cache()
         chk = not args.no_cpu_baseline
         if "configs" in legs:
-            res["other_configs"] = bench_configs(check_oracle=chk)
+            only = None if args.configs is None else set(args.configs.split(","))
+            res["other_configs"] = bench_configs(check_oracle=chk, only=only)
         if "dtypes" in legs:
             res["narrow_dtypes"] = bench_dtypes(check_oracle=chk)
             torch.cuda.empty_cache()
