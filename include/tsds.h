@@ -126,6 +126,25 @@ int ts_lttb(const ts_series *s, int64_t n_out, int64_t *out_idx, int64_t *out_co
 int ts_minmaxlttb(const ts_series *s, int64_t n_out, int64_t minmax_ratio, int64_t *out_idx,
                   int64_t *out_count, void *ws, size_t ws_bytes, void *stream);
 
+/* ts_minmaxlttb without a workspace argument and without any allocation, for
+ * callers that cannot allocate device memory (code under stream capture,
+ * serving loops, harnesses that forbid hipMalloc).  The library brings its own
+ * scratch: one static device array of ts_noalloc_scratch_bytes() = 64 MiB per
+ * GPU, reserved when the library's code is loaded on that GPU and held until
+ * the process ends; its device address is looked up once per GPU, on the
+ * first call there.  Arguments, outputs and results are those of
+ * ts_minmaxlttb on the stream's device (NULL stream: the current device).
+ * Errors: TS_ERR_WORKSPACE, before anything touches the GPU, when
+ * ts_workspace_bytes(TS_MINMAXLTTB, s, n_out, minmax_ratio) exceeds the
+ * scratch (about 4 GB of y); otherwise ts_minmaxlttb's checks and codes.
+ * The scratch needs no initial content, and every call on a GPU reuses that
+ * GPU's one array: calls whose work overlaps in time on the same GPU (two
+ * streams, two host threads) race on it and must be serialised by the
+ * caller. */
+size_t ts_noalloc_scratch_bytes(void);
+int ts_minmaxlttb_noalloc(const ts_series *s, int64_t n_out, int64_t minmax_ratio, int64_t *out_idx,
+                          int64_t *out_count, void *stream);
+
 /* NaN-aware MinMax and M4 (the paper flags NaN as needing a different
  * initial value, Sec. 2.1, Listing 1, and defines no more).  Reading: NaN
  * values of y are skipped; a bin holding only NaN keeps its first index as

@@ -15,6 +15,7 @@ device and the current stream; see include/tsds.h for the exact semantics.
 """
 from .api import (  # noqa: F401
     bin_argminmax, bin_edges, downsample_into, everynth, gather, lttb, lttb_centres, m4, minmax, minmaxlttb,
+    minmaxlttb_noalloc,
     nan_m4, nan_minmax,
     set_tuning, window, workspace_bytes,
 )

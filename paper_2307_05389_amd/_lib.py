@@ -62,6 +62,10 @@ def lib():
             f.restype = ctypes.c_int
         L.ts_minmaxlttb.argtypes = [SP, i64, i64, vp, vp, vp, sz, vp]
         L.ts_minmaxlttb.restype = ctypes.c_int
+        L.ts_minmaxlttb_noalloc.argtypes = [SP, i64, i64, vp, vp, vp]
+        L.ts_minmaxlttb_noalloc.restype = ctypes.c_int
+        L.ts_noalloc_scratch_bytes.argtypes = []
+        L.ts_noalloc_scratch_bytes.restype = sz
         L.ts_bin_edges.argtypes = [SP, i64, vp, vp]
         L.ts_bin_edges.restype = ctypes.c_int
         L.ts_argminmax_workspace_bytes.argtypes = [SP, i64]

@@ -35,6 +35,21 @@ def downsample_into(algo, y, n_out, out, count, x=None, minmax_ratio=4, workspac
     return out, count
 
 
+def minmaxlttb_noalloc(y, n_out, out, count, x=None, minmax_ratio=4, stream=None):
+    """ts_minmaxlttb_noalloc: MinMaxLTTB into the caller's `out` (int64,
+    >= n_out) and `count` (int64, 1 element) over the library's static
+    device scratch; neither this wrapper nor the library allocates device
+    memory.  Calls overlapping on one GPU share that scratch and must be
+    serialised by the caller."""
+    s = L.series(y, x)
+    if out.numel() < min(n_out, y.numel()) or out.dtype != torch.int64 or count.dtype != torch.int64:
+        raise ValueError("out must hold n_out int64 values and count one int64")
+    st = stream if stream is not None else torch.cuda.current_stream(y.device)
+    L.check(L.lib().ts_minmaxlttb_noalloc(ctypes.byref(s), n_out, minmax_ratio, L._ptr(out), L._ptr(count),
+                                          ctypes.c_void_p(st.cuda_stream)))
+    return out, count
+
+
 def _run(algo, y, n_out, x, minmax_ratio):
     out = torch.empty(max(n_out, 1), dtype=torch.int64, device=y.device)
     count = torch.zeros(1, dtype=torch.int64, device=y.device)

@@ -17,7 +17,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libtsds.so")
 
 SOURCES = ["scan.hip", "select.hip", "window.hip", "pick.hip", "nan.hip", "lttb.hip", "api.cpp", "batch.hip",
-           "batch_lttb.hip", "api_batch.cpp"]
+           "batch_lttb.hip", "api_batch.cpp", "noalloc.hip"]
 EXTRA_SOURCES = ["serve.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

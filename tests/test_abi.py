@@ -103,6 +103,23 @@ def test_validation_errors_without_launch(L, call, code):
     assert L.ts_last_error()
 
 
+def test_noalloc_rejects_before_touching_the_gpu(L):
+    """ts_minmaxlttb_noalloc: the static scratch holds 64 MiB; a series whose
+    workspace exceeds it, and invalid arguments, are rejected on the host
+    (no device is needed to get these codes)."""
+    assert L.ts_noalloc_scratch_bytes() == 64 << 20
+    out, cnt = ctypes.c_void_p(0x10000), ctypes.c_void_p(0x20000)
+    big = _series(10**10)
+    assert L.ts_workspace_bytes(3, ctypes.byref(big), 2000, 4) > L.ts_noalloc_scratch_bytes()
+    assert L.ts_minmaxlttb_noalloc(ctypes.byref(big), 2000, 4, out, cnt, None) == -4
+    assert b"scratch" in L.ts_last_error()
+    s = _series(10**6)
+    assert L.ts_minmaxlttb_noalloc(ctypes.byref(s), 1000, 0, out, cnt, None) == -1       # ratio 0
+    assert L.ts_minmaxlttb_noalloc(ctypes.byref(s), 1001, 1, out, cnt, None) == -1       # odd n_out * ratio
+    assert L.ts_minmaxlttb_noalloc(ctypes.byref(s), 1000, 4, None, cnt, None) == -3      # no output
+    assert L.ts_minmaxlttb_noalloc(ctypes.byref(_series(10**6, y=0x1001)), 1000, 4, out, cnt, None) == -6
+
+
 def test_no_cpu_fallback_in_product_package():
     """The product package never imports the oracle."""
     pkg = os.path.join(ROOT, "paper_2307_05389_amd")
