@@ -357,16 +357,23 @@ void ts_server_free(ts_server *server);
  * xclass (-1 = automatic: on for int64 x when bins average at least two
  * chunks, 0 = off, 1 = on; int64 x and unstaged scans only) lets each chunk
  * find its bins from x directly, so that the edge array is written by the scan
- * instead of a separate edge search.
+ * instead of a separate edge search; direct (-1 = automatic: small series,
+ * and series without x whose bins are 2-64 KB, at least 2048 of them; 0 =
+ * off, 1 = on for every MinMax / M4 call and preselection) gives each bin one
+ * wavefront that reduces the whole bin and writes its selection (no chunks,
+ * partials or merge; any other override set switches the automatic choice
+ * off).
  * Results never depend on them; workspace sizes do, so query
  * ts_workspace_bytes after a change.  Not thread-safe with concurrent
  * compute calls. */
-int ts_set_tuning(int64_t chunk_bytes, int32_t small_bin, int32_t scan_variant, int32_t stage, int32_t xclass);
+int ts_set_tuning(int64_t chunk_bytes, int32_t small_bin, int32_t scan_variant, int32_t stage, int32_t xclass,
+                  int32_t direct);
 
 /* Host-side query: the scan's tile variant, chunk size (bytes) and kind
  * (0 = chunks with an edge array or closed-form bins, 1 = LDS-staged,
- * 2 = classified from int64 x, 3 = chunks streamed tile by tile over their bins) for n elements of y_dtype in nb bins, x of
- * x_dtype (TS_NONE: no x), under the current tuning. */
+ * 2 = classified from int64 x, 3 = chunks streamed tile by tile over their
+ * bins, 4 = one wavefront per bin, no chunks) for n elements of y_dtype in nb
+ * bins, x of x_dtype (TS_NONE: no x), under the current tuning. */
 int ts_scan_config(int y_dtype, int x_dtype, int64_t n, int64_t nb, int32_t *variant, int64_t *chunk_bytes,
                    int32_t *kind);
 

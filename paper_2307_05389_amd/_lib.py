@@ -80,7 +80,7 @@ def lib():
         L.ts_everynth.restype = ctypes.c_int
         L.ts_gather.argtypes = [SP, vp, vp, i64, vp, vp, vp]
         L.ts_gather.restype = ctypes.c_int
-        L.ts_set_tuning.argtypes = [i64, i32, i32, i32, i32]
+        L.ts_set_tuning.argtypes = [i64, i32, i32, i32, i32, i32]
         L.ts_set_tuning.restype = ctypes.c_int
         L.ts_scan_config.argtypes = [ctypes.c_int, ctypes.c_int, i64, i64, ctypes.POINTER(ctypes.c_int32),
                                      ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)]
@@ -107,6 +107,9 @@ def scan_config(dtype, n, nb=1, x_dtype=None):
     check(lib().ts_scan_config(DTYPE_CODES[dtype], xd, int(n), int(nb), ctypes.byref(v), ctypes.byref(c),
                                ctypes.byref(k)))
     ct = CTYPE_NAME[DTYPE_CODES[dtype]]
+    if k.value == 4:
+        u, nbuf = VARIANT_SHAPE[v.value]
+        return v.value, c.value, f"tsds::k_bins_direct<{ct}, {u}, {nbuf}>"
     if k.value == 1:
         return v.value, c.value, f"tsds::k_scan_staged<{ct}>"
     if k.value == 3:

@@ -162,9 +162,11 @@ def window(x, xa, xb, y=None):
     return r
 
 
-def set_tuning(chunk_bytes=-1, small_bin=-1, scan_variant=-1, stage=-1, xclass=-1):
+def set_tuning(chunk_bytes=-1, small_bin=-1, scan_variant=-1, stage=-1, xclass=-1, direct=-1):
     """Override the scan's chunk size (power of two >= 4096 bytes), the
     segment length below which one lane handles a whole bin, the tile shape
-    variant, LDS staging and the classification of chunks from int64 x; -1
-    restores the defaults.  Results do not depend on them."""
-    L.check(L.lib().ts_set_tuning(int(chunk_bytes), int(small_bin), int(scan_variant), int(stage), int(xclass)))
+    variant, LDS staging, the classification of chunks from int64 x and the
+    one-wavefront-per-bin path; -1 restores the defaults.  Results do not
+    depend on them."""
+    L.check(L.lib().ts_set_tuning(int(chunk_bytes), int(small_bin), int(scan_variant), int(stage), int(xclass),
+                                  int(direct)))

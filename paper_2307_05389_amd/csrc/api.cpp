@@ -81,11 +81,48 @@ static int32_t g_small_override = -1;
 static int32_t g_variant_override = -1;
 static int32_t g_stage_override = -1;
 static int32_t g_xclass_override = -1;
+static int32_t g_direct_override = -1;
 
-// Series of at most kDirectMaxBytes in at least kDirectMinBins bins of at
-// least kDirectMinBin elements: one wavefront per bin instead of chunks (the
-// call is launch-bound there; two launches instead of three).
+// One wavefront per bin instead of chunks (two launches instead of three, no
+// per-chunk partials): series of at most kDirectMaxBytes in at least
+// kDirectMinBins bins of at least kDirectMinBin elements (the call is
+// launch-bound there), and series without x (equal bins, so every wavefront
+// reads the same amount) in at least kDirectWideMinBins bins of
+// kDirectWideMinBinBytes..kDirectWideMaxBinBytes.  Sweeps of MinMax over 1 GB
+// series on MI355X (u8, i16, f16, f32, f64; bins of 5 KB to 1 MB): from 5 KB
+// to 333 KB bins the per-bin wavefront is the fastest path for every type
+// (10 KB u8 bins 3.2 -> 4.3 TB/s, 10 KB f32 bins 4.7 -> 6.0 TB/s); below
+// ~4 KB the LDS-staged chunks win, and with ~1,000 bins there are too few
+// wavefronts and the chunked scan wins.
 static const int64_t kDirectMaxBytes = 8 << 20, kDirectMinBins = 64, kDirectMinBin = 256;
+static const int64_t kDirectWideMinBins = 2048, kDirectWideMinBinBytes = 4096, kDirectWideMaxBinBytes = 512 << 10;
+
+// The per-bin grid has 64 threads per bin: at most 2^25 bins keeps it within
+// 2^31 threads.
+static const int64_t kDirectMaxBinCount = (int64_t)1 << 25;
+
+// Tile shape of the per-bin kernel (the scan's variant numbering: 0 = 4x2,
+// 1 = 4x1, 2 = 8x1, 3 = 2x2) from the same sweeps: bins under 8 KB take
+// small tiles two in flight; one- and two-byte types 4x1 (their fold needs
+// the most registers: 4x2 halves the wavefronts per SIMD); four- and
+// eight-byte types 4x2, 8x1 from 32 KB bins.
+static int32_t direct_variant(int ydt, int64_t bin_bytes) {
+  if (bin_bytes < 8192) return 3;
+  if (elem_size(ydt) <= 2) return 1;
+  return bin_bytes >= 32768 ? 2 : 0;
+}
+
+static bool direct_bins(int ydt, bool has_x, int64_t n, int64_t nb) {
+  if (nb > kDirectMaxBinCount) return false;
+  if (g_direct_override >= 0) return g_direct_override == 1;
+  if (g_chunk_bytes_override >= 0 || g_small_override >= 0 || g_variant_override >= 0 || g_stage_override >= 0)
+    return false;  // explicit chunk tuning: the chunked kernels run
+  const int64_t es = (int64_t)elem_size(ydt);
+  if (n * es <= kDirectMaxBytes && nb >= kDirectMinBins && n / nb >= kDirectMinBin) return true;
+  const int64_t bin_bytes = n / nb * es;
+  return !has_x && nb >= kDirectWideMinBins && bin_bytes >= kDirectWideMinBinBytes &&
+         bin_bytes <= kDirectWideMaxBinBytes;
+}
 
 // Bins averaging fewer than kStageBin elements go through LDS-staged chunks
 // of kStageChunk bytes (one HBM round trip per chunk instead of one per bin).
@@ -119,7 +156,7 @@ static const int64_t kXclassChunks = 2;
 static ScanShape scan_shape(int ydt, int xdt, int64_t n, int64_t nb) {
   const int64_t total = n * (int64_t)elem_size(ydt);
   const int32_t stage = g_stage_override >= 0 ? g_stage_override : (nb > 0 && n / nb < kStageBin ? 1 : 0);
-  if (xdt == TS_I64 && !stage && g_xclass_override != 0) {
+  if (xdt == TS_I64 && !stage && g_xclass_override != 0 && g_direct_override != 1) {
     ScanShape sh = xclass_shape(ydt);
     if (g_variant_override >= 0) sh.variant = g_variant_override;
     sh.chunk_bytes = g_chunk_bytes_override > 0 ? g_chunk_bytes_override : fit_chunk(sh.chunk_bytes, total, 2048);
@@ -378,10 +415,8 @@ static int run_scan(const ts_series &s, int64_t nb, int m4, const ScanPlan &pl, 
   sp.x = pl.xclass ? s.x : nullptr;
   sp.xedges = pl.xclass ? ed : nullptr;
   if (pl.xclass) sp.edges = nullptr;
-  // small series without tuning overrides: one wavefront per bin, no merge
-  const bool direct = !pl.nan && !pl.xclass && s.n * (int64_t)elem_size(s.y_dtype) <= kDirectMaxBytes && nb >= kDirectMinBins &&
-                      s.n / nb >= kDirectMinBin && g_chunk_bytes_override < 0 && g_small_override < 0 &&
-                      g_variant_override < 0 && g_stage_override < 0 && !g_ev_start;
+  // one wavefront per bin, no merge (not while the scan kernel is being timed)
+  const bool direct = !pl.nan && !pl.xclass && !g_ev_start && direct_bins(s.y_dtype, s.x != nullptr, s.n, nb);
   if (pl.nan) {
     if ((e = launch_scan_nan(s.y_dtype, sp, st)) != hipSuccess) return hip_fail(e, "nan scan");
   } else if (!direct && (e = launch_scan(s.y_dtype, sp, st, g_ev_start, g_ev_stop)) != hipSuccess) {
@@ -410,7 +445,11 @@ static int run_scan(const ts_series &s, int64_t nb, int m4, const ScanPlan &pl, 
   cp.all_n = -1;
   cp.bsum = nb > kCompactSingleMax ? (int64_t *)wsp(ws, pl.off_bsum) : nullptr;
   if (direct) {
-    if ((e = launch_bins_direct(s.y_dtype, sp, mp, st)) != hipSuccess) return hip_fail(e, "bins");
+    ScanParams dp = sp;
+    dp.variant = g_variant_override >= 0 && g_variant_override < kScanStreamVariant
+                     ? g_variant_override
+                     : direct_variant(s.y_dtype, s.n / nb * (int64_t)elem_size(s.y_dtype));
+    if ((e = launch_bins_direct(s.y_dtype, dp, mp, st)) != hipSuccess) return hip_fail(e, "bins");
   } else if ((e = launch_merge(mp, st)) != hipSuccess) {
     return hip_fail(e, "merge");
   }
@@ -743,12 +782,15 @@ int ts_gather(const ts_series *s, const int64_t *idx, const int64_t *count, int6
 }
 
 // Tuning knobs (tests use them to show that results do not depend on them).
-int ts_set_tuning(int64_t chunk_bytes, int32_t small_bin, int32_t scan_variant, int32_t stage, int32_t xclass) {
+int ts_set_tuning(int64_t chunk_bytes, int32_t small_bin, int32_t scan_variant, int32_t stage, int32_t xclass,
+                  int32_t direct) {
   if (chunk_bytes > 0 && (chunk_bytes < 4096 || (chunk_bytes & (chunk_bytes - 1))))
     return fail(TS_ERR_ARG, "chunk_bytes must be a power of two >= 4096");
   if (scan_variant > kScanStreamVariant) return fail(TS_ERR_ARG, "scan_variant must be -1..4");
   if (stage > 1) return fail(TS_ERR_ARG, "stage must be -1, 0 or 1");
   if (xclass > 1) return fail(TS_ERR_ARG, "xclass must be -1, 0 or 1");
+  if (direct > 1) return fail(TS_ERR_ARG, "direct must be -1, 0 or 1");
+  g_direct_override = direct < 0 ? -1 : direct;
   g_chunk_bytes_override = chunk_bytes;
   g_small_override = small_bin;
   g_variant_override = scan_variant;
@@ -767,6 +809,12 @@ int ts_scan_config(int y_dtype, int x_dtype, int64_t n, int64_t nb, int32_t *var
   *variant = sh.variant;
   *chunk_bytes = sh.chunk_bytes;
   *kind = sh.stage ? 1 : sh.xclass ? 2 : sh.variant == kScanStreamVariant ? 3 : 0;
+  if (!sh.xclass && direct_bins(y_dtype, x_dtype != TS_NONE, n, nb)) {
+    *kind = 4;
+    *variant = g_variant_override >= 0 && g_variant_override < kScanStreamVariant
+                   ? g_variant_override
+                   : direct_variant(y_dtype, n / nb * (int64_t)elem_size(y_dtype));
+  }
   return TS_OK;
 }
 

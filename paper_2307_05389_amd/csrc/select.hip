@@ -54,9 +54,10 @@ __global__ __launch_bounds__(256) void k_merge_lanes(MergeParams p) {
   p.cnt[bin] = bin_selection(s, e, imn, imx, p.m4, p.sel + 4 * bin);
 }
 
-// Small series: one wavefront per bin reduces the whole bin and writes its
-// selection, so no per-chunk partials and no merge launch are needed.
-template <typename T>
+// One wavefront per bin reduces the whole bin (U vectors per lane per tile,
+// NB tiles in flight) and writes its selection, so no per-chunk partials and
+// no merge launch are needed.
+template <typename T, int U, int NB>
 __global__ __launch_bounds__(256) void k_bins_direct(ScanParams sp, MergeParams mp) {
   const int64_t bin = uniform((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6));
   if (bin >= mp.nb) return;
@@ -68,26 +69,39 @@ __global__ __launch_bounds__(256) void k_bins_direct(ScanParams sp, MergeParams 
     return;
   }
   const u32x4 *__restrict__ base = (const u32x4 *)((const T *)sp.y - sp.shift);
-  u32x4 buf[2][4];
+  u32x4 buf[NB][U];
   SegState<typename Elem<T>::C> st;
-  wave_segment<T, 4, 2>(base, sp.shift, s, e, lane, buf, 0, st);
+  wave_segment<T, U, NB>(base, sp.shift, s, e, lane, buf, 0, st);
   if (lane == 0) mp.cnt[bin] = bin_selection(s, e, st.imn, st.imx, mp.m4, mp.sel + 4 * bin);
 }
 
+template <typename T>
+static void launch_direct_t(int variant, dim3 grid, dim3 block, const ScanParams &sp, const MergeParams &mp,
+                            hipStream_t st) {
+  switch (variant) {
+    case 1: k_bins_direct<T, 4, 1><<<grid, block, 0, st>>>(sp, mp); break;
+    case 2: k_bins_direct<T, 8, 1><<<grid, block, 0, st>>>(sp, mp); break;
+    case 3: k_bins_direct<T, 2, 2><<<grid, block, 0, st>>>(sp, mp); break;
+    default: k_bins_direct<T, 4, 2><<<grid, block, 0, st>>>(sp, mp); break;
+  }
+}
+
+// sp.variant picks the tile shape (0 = 4x2, 1 = 4x1, 2 = 8x1, 3 = 2x2).
 hipError_t launch_bins_direct(int ydt, const ScanParams &sp, const MergeParams &mp, hipStream_t st) {
   const dim3 grid((unsigned)((mp.nb + 3) / 4)), block(256);
+  const int v = sp.variant;
   switch (ydt) {
-    case TS_I8: k_bins_direct<int8_t><<<grid, block, 0, st>>>(sp, mp); break;
-    case TS_I16: k_bins_direct<int16_t><<<grid, block, 0, st>>>(sp, mp); break;
-    case TS_I32: k_bins_direct<int32_t><<<grid, block, 0, st>>>(sp, mp); break;
-    case TS_I64: k_bins_direct<int64_t><<<grid, block, 0, st>>>(sp, mp); break;
-    case TS_U8: k_bins_direct<uint8_t><<<grid, block, 0, st>>>(sp, mp); break;
-    case TS_U16: k_bins_direct<uint16_t><<<grid, block, 0, st>>>(sp, mp); break;
-    case TS_U32: k_bins_direct<uint32_t><<<grid, block, 0, st>>>(sp, mp); break;
-    case TS_U64: k_bins_direct<uint64_t><<<grid, block, 0, st>>>(sp, mp); break;
-    case TS_F16: k_bins_direct<half_t><<<grid, block, 0, st>>>(sp, mp); break;
-    case TS_F32: k_bins_direct<float><<<grid, block, 0, st>>>(sp, mp); break;
-    case TS_F64: k_bins_direct<double><<<grid, block, 0, st>>>(sp, mp); break;
+    case TS_I8: launch_direct_t<int8_t>(v, grid, block, sp, mp, st); break;
+    case TS_I16: launch_direct_t<int16_t>(v, grid, block, sp, mp, st); break;
+    case TS_I32: launch_direct_t<int32_t>(v, grid, block, sp, mp, st); break;
+    case TS_I64: launch_direct_t<int64_t>(v, grid, block, sp, mp, st); break;
+    case TS_U8: launch_direct_t<uint8_t>(v, grid, block, sp, mp, st); break;
+    case TS_U16: launch_direct_t<uint16_t>(v, grid, block, sp, mp, st); break;
+    case TS_U32: launch_direct_t<uint32_t>(v, grid, block, sp, mp, st); break;
+    case TS_U64: launch_direct_t<uint64_t>(v, grid, block, sp, mp, st); break;
+    case TS_F16: launch_direct_t<half_t>(v, grid, block, sp, mp, st); break;
+    case TS_F32: launch_direct_t<float>(v, grid, block, sp, mp, st); break;
+    case TS_F64: launch_direct_t<double>(v, grid, block, sp, mp, st); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

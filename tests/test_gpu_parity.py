@@ -170,6 +170,56 @@ def test_streamed_chunks(ts, oracle_mod, dtype):
         ts.set_tuning()
 
 
+def _direct_cases(ts, oracle_mod, y, x, off, tag):
+    n = len(y)
+    yd = dev(y)[off:]
+    for xx in (None, x[off:]):
+        xd = None if xx is None else dev(xx)
+        for algo, n_out in (("minmax", 2), ("m4", 4), ("minmax", 600), ("m4", 4000), ("minmax", 100000),
+                            ("minmax", 2 * n), ("minmaxlttb", 1000)):
+            say(f"[direct] {tag} off={off} x={xx is not None} {algo} {n_out}")
+            if algo == "minmaxlttb":
+                got = ts.minmaxlttb(yd, n_out, x=xd, minmax_ratio=4)
+            else:
+                got = getattr(ts, algo)(yd, n_out, x=xd)
+            torch.cuda.synchronize()
+            want = orc(oracle_mod, algo, y[off:], n_out, xx, 4)
+            assert np.array_equal(got.cpu().numpy(), want), (algo, n_out, off)
+
+
+@pytest.mark.parametrize("dtype", [np.uint8, np.int8, np.int16, np.float16, np.float32, np.int32, np.float64,
+                                   np.uint64])
+def test_direct_bins(ts, oracle_mod, dtype):
+    """One wavefront per bin reducing the whole bin (no chunks, no merge):
+    forced on for bins of one element to the whole series, with and without
+    x, off the 16-byte grid; and chosen automatically for series without x
+    above the small-series limit whose bins are a few kilobytes."""
+    n = 300_007
+    y = S.walk(n, dtype, seed=81)
+    S.tie_runs(y, 0.1, seed=82)
+    x = S.timestamps(n, 40, seed=83)
+    try:
+        for variant in (-1, 0, 1, 2, 3):     # the automatic tile shape, then each shape
+            ts.set_tuning(direct=1, scan_variant=variant)
+            for off in ((0, 5) if variant == -1 else (5,)):
+                _direct_cases(ts, oracle_mod, y, x, off, f"{np.dtype(dtype).name} variant={variant}")
+    finally:
+        ts.set_tuning()
+    # automatic choice: > 8 MB, no x, >= 2048 bins of 4-512 KB
+    es = np.dtype(dtype).itemsize
+    nbig = (16 << 20) // es + 13
+    ybig = S.walk(nbig, dtype, seed=84)
+    for bin_bytes in (4096, 5000, 8192):
+        nb = nbig * es // bin_bytes
+        if nb < 2048:
+            continue
+        from paper_2307_05389_amd import _lib as L
+        assert L.scan_config(dev(ybig[:8]).dtype, nbig, nb)[2].startswith("tsds::k_bins_direct<")
+        for algo, per in (("minmax", 2), ("m4", 4)):
+            say(f"[direct auto] {np.dtype(dtype).name} bin_bytes={bin_bytes} {algo}")
+            assert np.array_equal(gpu(ts, algo, ybig, per * nb), orc(oracle_mod, algo, ybig, per * nb))
+
+
 def x_patterns(n, seed):
     """int64 x layouts that stress finding bins from x: steady timestamps,
     long gaps (runs of empty bins, some spanning many chunks), runs of equal
