@@ -206,117 +206,357 @@ __global__ __launch_bounds__(256) void k_centres(LttbParams p) {
   }
 }
 
-// Centres of a plain series with long buckets, one wavefront per bucket.
-// The wavefront reads the bucket a tile at a time (kCentreBatch consecutive
-// points per lane; the loads of the next tile are in flight while the current
-// one is added).  Integer coordinates: every lane adds its points exactly in
-// 128 bits and lane 0 adds the 64 partial sums (exact, so the order is free).
-// Float coordinates: the tile is staged in LDS as doubles (converted by all
-// lanes) and lane 0 adds it strictly in index order, as the sequential loop
-// does.  The index coordinate has a
-// closed form.
+// Centres of a plain series with long buckets, one workgroup per bucket.
+//
+// The sequential double sum of float coordinates (the rounding the centres
+// must reproduce) is evaluated without walking every point in turn.  Every
+// finite double is odd * 2^q; when a run of terms and the running sum s are
+// all multiples of 2^q' (q' the smallest such exponent among them) and
+// |s| + sum |v| < 2^(q' + 53), every partial sum of the run is a multiple of
+// 2^q' below 2^(q' + 53), hence exactly representable: the sequential loop
+// then makes no rounding at all over the run, and s + (the run's sum, added
+// in any order) is the same double.  Whether a run qualifies is decided
+// exactly from the same quantities computed in floating point: all terms are
+// non-negative multiples of 2^q', so a computed sum of them reaches
+// 2^(q' + 53) if and only if the exact sum does.
+//
+// The workgroup's wavefronts summarise tiles of kCentreTile consecutive
+// points (coalesced loads, any order): sum, sum of |v|, smallest exponent q,
+// or the exact 128-bit sum for integer coordinates.  Wavefront 0 then folds
+// the tile summaries into the running sum in index order, one addition per
+// tile that qualifies; a tile that does not is staged in LDS in index order
+// and folded per 16-point segment, a segment that does not qualify point by
+// point.  The result is bit-identical to the plain loop.  The index
+// coordinate has a closed form.
 constexpr int kCentreBatch = 16;
 constexpr int kCentreTile = 64 * kCentreBatch;
+constexpr int kCentreRound = 128;       // tile summaries held in LDS at a time
+constexpr int kNoExp = 0x7fffffff;      // exponent of a run of zeros
 
 __device__ inline bool float_dtype(int dt) { return dt == TS_F16 || dt == TS_F32 || dt == TS_F64; }
 
-// acc + b[0] + b[1] + ... + b[cnt-1], left to right.
-__device__ inline double seq_sum(const double *b, int cnt, double acc) {
-  int j = 0;
-  for (; j + 8 <= cnt; j += 8) {
-    double v[8];
-#pragma unroll
-    for (int u = 0; u < 8; u++) v[u] = b[j + u];
-#pragma unroll
-    for (int u = 0; u < 8; u++) acc += v[u];
-  }
-  for (; j < cnt; j++) acc += b[j];
-  return acc;
+// q with v = odd * 2^q, for finite nonzero v.
+__device__ inline int trailing_exp(double v) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const int e = (int)((b >> 52) & 0x7ff);
+  const uint64_t f = b & ((1ull << 52) - 1);
+  return e == 0 ? -1074 + __builtin_ctzll(f) : e - 1075 + __builtin_ctzll(f | (1ull << 52));
 }
 
-__global__ __launch_bounds__(64) void k_centres_wave(LttbParams p) {
-  __shared__ double tile[2][kCentreTile];  // float coordinates as doubles: [0] Y, [1] X
-  __shared__ __int128 part[2][64];
-  const int lane = threadIdx.x;
+// True when adding terms that are multiples of 2^qa with absolute sum a to
+// the running sum s makes no rounding (see above).
+__device__ inline bool adds_exactly(double s, double a, int qa) {
+  const int qs = s == 0.0 ? kNoExp : trailing_exp(s);
+  const int q = qs < qa ? qs : qa;
+  if (q == kNoExp) return true;  // zeros only
+  const double t = __builtin_fabs(s) + a;
+  if (q + 53 >= 1024) return t < __builtin_huge_val();
+  return t < __builtin_bit_cast(double, (uint64_t)(q + 53 + 1023) << 52);
+}
+
+__device__ inline double wave_sum_dbl(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ inline int wave_min_int(int v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    const int w = __shfl_xor(v, o, 64);
+    v = w < v ? w : v;
+  }
+  return v;
+}
+__device__ inline __int128 wave_sum_i128(__int128 v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    const uint64_t lo = __shfl_xor((uint64_t)v, o, 64);
+    const uint64_t hi = __shfl_xor((uint64_t)((unsigned __int128)v >> 64), o, 64);
+    v += (__int128)(((unsigned __int128)hi << 64) | lo);
+  }
+  return v;
+}
+
+// Raw bits of elements j0 + u*64 + lane (u < kCentreBatch) below hi, 0 past
+// it (R: 32-bit words for elements of up to 4 bytes, 64-bit for 8).
+template <typename R>
+__device__ inline void load_strided(const void *a, int es, int64_t j0, int64_t hi, int lane, R (&r)[kCentreBatch]) {
+#pragma unroll
+  for (int u = 0; u < kCentreBatch; u++) {
+    const int64_t j = j0 + u * 64 + lane;
+    R v = 0;
+    if (j < hi) {
+      if constexpr (sizeof(R) == 8) {
+        v = ((const uint64_t *)a)[j];
+      } else {
+        switch (es) {
+          case 1: v = ((const uint8_t *)a)[j]; break;
+          case 2: v = ((const uint16_t *)a)[j]; break;
+          default: v = ((const uint32_t *)a)[j]; break;
+        }
+      }
+    }
+    r[u] = v;
+  }
+}
+
+struct TileSums {
+  double s[kCentreRound], a[kCentreRound];
+  int q[kCentreRound];
+  __int128 i[kCentreRound];
+};
+
+template <typename R>
+__device__ inline void tile_summary_r(const void *a, int dt, int64_t j0, int64_t hi, int lane, TileSums &ts, int t) {
+  R r[kCentreBatch];
+  load_strided<R>(a, elem_bytes(dt), j0, hi, lane, r);
+  if (float_dtype(dt)) {
+    double sum = 0.0, abs = 0.0;
+    int q = kNoExp;
+#pragma unroll
+    for (int u = 0; u < kCentreBatch; u++) {
+      double w[1];
+      const R one[1] = {r[u]};
+      convert_raw(one, dt, w);
+      if (j0 + u * 64 + lane < hi) {
+        sum += w[0];
+        abs += __builtin_fabs(w[0]);
+        if (w[0] != 0.0) {
+          const int e = trailing_exp(w[0]);
+          q = e < q ? e : q;
+        }
+      }
+    }
+    sum = wave_sum_dbl(sum);
+    abs = wave_sum_dbl(abs);
+    q = wave_min_int(q);
+    if (lane == 0) {
+      ts.s[t] = sum;
+      ts.a[t] = abs;
+      ts.q[t] = q;
+    }
+  } else {
+    uint64_t r64[kCentreBatch];
+#pragma unroll
+    for (int u = 0; u < kCentreBatch; u++) r64[u] = (uint64_t)r[u];
+    __int128 acc = 0;
+    add_int_raw(r64, dt, 0, kCentreBatch, acc);  // elements past hi were loaded as 0
+    acc = wave_sum_i128(acc);
+    if (lane == 0) ts.i[t] = acc;
+  }
+}
+
+// Summary of tile [j0, min(j0 + kCentreTile, hi)) of one coordinate (sum,
+// sum of |v| and smallest exponent, or the exact integer sum), written to
+// slot t by lane 0.
+__device__ inline void tile_summary(const void *a, int dt, int64_t j0, int64_t hi, int lane, TileSums &ts, int t) {
+  if (elem_bytes(dt) == 8)
+    tile_summary_r<uint64_t>(a, dt, j0, hi, lane, ts, t);
+  else
+    tile_summary_r<uint32_t>(a, dt, j0, hi, lane, ts, t);
+}
+
+// Wavefront 0: the sequential sum continued over tile j0 point by point in
+// index order, exact runs of 16 points added at once.
+__device__ __noinline__ double fold_tile_points(const void *a, int dt, int64_t j0, int64_t hi, int lane, double run,
+                                                double *buf) {
+#pragma unroll
+  for (int u = 0; u < kCentreBatch; u++) {
+    const int64_t j = j0 + u * 64 + lane;
+    buf[u * 64 + lane] = j < hi ? dbl_val(a, dt, j) : 0.0;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  const int c = (int)(hi - j0 < kCentreTile ? hi - j0 : kCentreTile);
+  // segment of lane l: tile positions 16 l .. 16 l + 15
+  double sum = 0.0, abs = 0.0;
+  int q = kNoExp;
+  for (int u = 0; u < kCentreBatch; u++) {
+    const int i = lane * kCentreBatch + u;
+    if (i < c) {
+      const double w = buf[i];
+      sum += w;
+      abs += __builtin_fabs(w);
+      if (w != 0.0) {
+        const int e = trailing_exp(w);
+        q = e < q ? e : q;
+      }
+    }
+  }
+  for (int l = 0; l * kCentreBatch < c; l++) {
+    const double ls = __shfl(sum, l, 64), la = __shfl(abs, l, 64);
+    const int lq = __shfl(q, l, 64);
+    if (adds_exactly(run, la, lq)) {
+      run += ls;
+    } else {
+      const int e = (l + 1) * kCentreBatch < c ? (l + 1) * kCentreBatch : c;
+      for (int i = l * kCentreBatch; i < e; i++) run += buf[i];
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  return run;
+}
+
+// Per-lane running summary of the points a lane reads.
+struct LaneSum {
+  double s, a;
+  int q;
+  __int128 i;
+};
+__device__ inline LaneSum lane_sum_zero() {
+  LaneSum z;
+  z.s = 0.0;
+  z.a = 0.0;
+  z.q = kNoExp;
+  z.i = 0;
+  return z;
+}
+
+template <typename R>
+__device__ inline void lane_accumulate_r(const void *a, int dt, int64_t j0, int64_t hi, int lane, LaneSum &ls) {
+  R r[kCentreBatch];
+  load_strided<R>(a, elem_bytes(dt), j0, hi, lane, r);
+  if (float_dtype(dt)) {
+#pragma unroll
+    for (int u = 0; u < kCentreBatch; u++) {
+      double w[1];
+      const R one[1] = {r[u]};
+      convert_raw(one, dt, w);
+      if (j0 + u * 64 + lane < hi) {
+        ls.s += w[0];
+        ls.a += __builtin_fabs(w[0]);
+        if (w[0] != 0.0) {
+          const int e = trailing_exp(w[0]);
+          ls.q = e < ls.q ? e : ls.q;
+        }
+      }
+    }
+  } else {
+    uint64_t r64[kCentreBatch];
+#pragma unroll
+    for (int u = 0; u < kCentreBatch; u++) r64[u] = (uint64_t)r[u];
+    add_int_raw(r64, dt, 0, kCentreBatch, ls.i);  // elements past hi were loaded as 0
+  }
+}
+
+__device__ inline void lane_accumulate(const void *a, int dt, int64_t j0, int64_t hi, int lane, LaneSum &ls) {
+  if (elem_bytes(dt) == 8)
+    lane_accumulate_r<uint64_t>(a, dt, j0, hi, lane, ls);
+  else
+    lane_accumulate_r<uint32_t>(a, dt, j0, hi, lane, ls);
+}
+
+// Workgroup-wide sum of the lane summaries (a fixed tree order), in thread 0.
+template <int W>
+__device__ inline LaneSum block_sum(LaneSum v, int lane, int wv, LaneSum *red) {
+  v.s = wave_sum_dbl(v.s);
+  v.a = wave_sum_dbl(v.a);
+  v.q = wave_min_int(v.q);
+  v.i = wave_sum_i128(v.i);
+  if (lane == 0) red[wv] = v;
+  __syncthreads();
+  LaneSum t = red[0];
+  for (int w = 1; w < W; w++) {
+    t.s += red[w].s;
+    t.a += red[w].a;
+    t.q = red[w].q < t.q ? red[w].q : t.q;
+    t.i += red[w].i;
+  }
+  __syncthreads();
+  return t;
+}
+
+// The sequential sum of one float coordinate over [lo, hi), tile by tile
+// (wavefront 0 folds what the workgroup summarised), for buckets whose whole
+// sum is not exact.
+template <int W>
+__device__ double bucket_sum_by_tiles(const void *a, int dt, int64_t lo, int64_t hi, int lane, int wv, TileSums &ts,
+                                      double *buf) {
+  const int64_t ntiles = (hi - lo + kCentreTile - 1) / kCentreTile;
+  double run = 0.0;
+  for (int64_t r0 = 0; r0 < ntiles; r0 += kCentreRound) {
+    const int rn = (int)(ntiles - r0 < kCentreRound ? ntiles - r0 : kCentreRound);
+    for (int t = wv; t < rn; t += W) tile_summary(a, dt, lo + (r0 + t) * kCentreTile, hi, lane, ts, t);
+    __syncthreads();
+    if (wv == 0) {
+      for (int t0 = 0; t0 < rn; t0 += 64) {
+        const int t = t0 + lane;
+        const double ms = t < rn ? ts.s[t] : 0.0, ma = t < rn ? ts.a[t] : 0.0;
+        const int mq = t < rn ? ts.q[t] : kNoExp;
+        const int e = rn - t0 < 64 ? rn - t0 : 64;
+        for (int i = 0; i < e; i++) {
+          const double sa = __shfl(ma, i, 64);
+          const int sq = __shfl(mq, i, 64);
+          if (adds_exactly(run, sa, sq))
+            run += __shfl(ms, i, 64);
+          else
+            run = fold_tile_points(a, dt, lo + (r0 + t0 + i) * kCentreTile, hi, lane, run, buf);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  return run;  // meaningful in wavefront 0
+}
+
+template <int W>
+__global__ __launch_bounds__(64 * W) void k_centres_block(LttbParams p) {
+  __shared__ TileSums tsum;
+  __shared__ double buf[kCentreTile];   // a tile in index order (fallback)
+  __shared__ LaneSum red[W];
+  __shared__ int exact_sh[2];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int64_t m = p.m, nb = p.n_out - 2;
   const int64_t k = blockIdx.x;
   if (k == nb - 1) {
-    if (lane == 0) {
+    if (threadIdx.x == 0) {
       p.cx[k] = X_of(p, m - 1);
       p.cy[k] = Y_of(p, m - 1);
     }
     return;
   }
   const int64_t lo = bucket_start(k + 1, m, nb), hi = bucket_start(k + 2, m, nb);
-  const double cnt = (double)(hi - lo);
   const bool hx = p.x_dtype != TS_NONE;
   const bool fx = hx && float_dtype(p.x_dtype), fy = float_dtype(p.y_dtype);
-  const int ysb = elem_bytes(p.y_dtype), xsb = hx ? elem_bytes(p.x_dtype) : 0;
-  __int128 ix = 0, iy = 0;
-  double sx = 0.0, sy = 0.0;
-  const int off = lane * kCentreBatch;
-  uint64_t ry[kCentreBatch], rx[kCentreBatch];
-  load_raw(p.y, ysb, lo + off, hi - 1, ry);
-  if (hx) load_raw(p.x, xsb, lo + off, hi - 1, rx);
-  for (int64_t t0 = lo; t0 < hi; t0 += kCentreTile) {
-    const int64_t j0 = t0 + off;
-    if (fy) {
-      double v[kCentreBatch];
-      convert_raw(ry, p.y_dtype, v);  // converted by all lanes, added by one
-#pragma unroll
-      for (int u = 0; u < kCentreBatch; u++) tile[0][off + u] = v[u];
-    } else {
-      add_int_raw(ry, p.y_dtype, j0, hi, iy);
-    }
-    if (fx) {
-      double v[kCentreBatch];
-      convert_raw(rx, p.x_dtype, v);
-#pragma unroll
-      for (int u = 0; u < kCentreBatch; u++) tile[1][off + u] = v[u];
-    } else if (hx) {
-      add_int_raw(rx, p.x_dtype, j0, hi, ix);
-    }
-    __syncthreads();
-    load_raw(p.y, ysb, j0 + kCentreTile, hi - 1, ry);
-    if (hx) load_raw(p.x, xsb, j0 + kCentreTile, hi - 1, rx);
-    const int c = (int)(hi - t0 < kCentreTile ? hi - t0 : kCentreTile);
-    if (lane == 0) {
-      if (fy) sy = seq_sum(tile[0], c, sy);
-      if (fx) sx = seq_sum(tile[1], c, sx);
-    }
-    __syncthreads();
+  const int64_t ntiles = (hi - lo + kCentreTile - 1) / kCentreTile;
+  // Whole bucket: lane summaries over tiles wv, wv + W, ...
+  LaneSum ly = lane_sum_zero(), lx = lane_sum_zero();
+  for (int64_t t = wv; t < ntiles; t += W) {
+    const int64_t j0 = lo + t * kCentreTile;
+    lane_accumulate(p.y, p.y_dtype, j0, hi, lane, ly);
+    if (hx) lane_accumulate(p.x, p.x_dtype, j0, hi, lane, lx);
   }
-  part[0][lane] = ix;
-  part[1][lane] = iy;
+  const LaneSum by = block_sum<W>(ly, lane, wv, red);
+  const LaneSum bx = hx ? block_sum<W>(lx, lane, wv, red) : lane_sum_zero();
+  // The sum in any order equals the sequential one when no partial sum can
+  // round; otherwise fold tile by tile.
+  if (threadIdx.x == 0) {
+    exact_sh[0] = !fy || adds_exactly(0.0, by.a, by.q);
+    exact_sh[1] = !fx || adds_exactly(0.0, bx.a, bx.q);
+  }
   __syncthreads();
-  if (lane == 0) {
-    double my, mx;
-    if (fy) {
-      my = sy / cnt;
-    } else {
-      __int128 t = 0;
-      for (int i = 0; i < 64; i++) t += part[1][i];
-      my = i128_to_double(t) / cnt;
-    }
-    if (!hx) {
-      mx = i128_to_double(((__int128)lo + (__int128)hi - 1) * (__int128)(hi - lo) / 2) / cnt;
-    } else if (fx) {
-      mx = sx / cnt;
-    } else {
-      __int128 t = 0;
-      for (int i = 0; i < 64; i++) t += part[0][i];
-      mx = i128_to_double(t) / cnt;
-    }
-    p.cy[k] = my;
-    p.cx[k] = mx;
+  double sy = by.s, sx = bx.s;
+  if (!exact_sh[0]) sy = bucket_sum_by_tiles<W>(p.y, p.y_dtype, lo, hi, lane, wv, tsum, buf);
+  if (!exact_sh[1]) sx = bucket_sum_by_tiles<W>(p.x, p.x_dtype, lo, hi, lane, wv, tsum, buf);
+  if (threadIdx.x == 0) {
+    const double cnt = (double)(hi - lo);
+    p.cy[k] = fy ? sy / cnt : i128_to_double(by.i) / cnt;
+    if (!hx)
+      p.cx[k] = i128_to_double(((__int128)lo + (__int128)hi - 1) * (__int128)(hi - lo) / 2) / cnt;
+    else
+      p.cx[k] = fx ? sx / cnt : i128_to_double(bx.i) / cnt;
   }
 }
 
 hipError_t launch_lttb_centres(const LttbParams &p, hipStream_t st) {
   const int64_t nb = p.n_out - 2;
-  if (!p.sel && p.m >= 0 && (p.m - 2) / nb >= kHullMinBucket)
-    k_centres_wave<<<dim3((unsigned)nb), dim3(64), 0, st>>>(p);
-  else
+  if (!p.sel && p.m >= 0 && (p.m - 2) / nb >= kHullMinBucket) {
+    if ((p.m - 2) / nb >= 8 * kCentreTile)
+      k_centres_block<8><<<dim3((unsigned)nb), dim3(512), 0, st>>>(p);
+    else
+      k_centres_block<2><<<dim3((unsigned)nb), dim3(128), 0, st>>>(p);
+  } else
     k_centres<<<dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, st>>>(p);
   return hipGetLastError();
 }

@@ -464,6 +464,54 @@ def test_lttb_centres_bit_exact(ts, oracle_mod):
             assert np.array_equal(cx.cpu().numpy(), ecx) and np.array_equal(cy.cpu().numpy(), ecy)
 
 
+def _bits_equal(a, b):
+    a, b = np.asarray(a, np.float64), np.asarray(b, np.float64)
+    return a.shape == b.shape and np.array_equal(a.view(np.uint64), b.view(np.uint64))
+
+
+def _centre_cases(n, seed):
+    """Float series whose bucket sums are exact in some tiles and rounded in
+    others: a walk crossing zero (tiny values beside large partial sums),
+    full-mantissa float64 noise (every tile rounds), mixed magnitudes, exact
+    small integers, all negative zeros, and +-inf (a NaN centre)."""
+    rng = np.random.default_rng(seed)
+    walk = S.walk(n, np.float32, seed=seed)
+    noise = rng.standard_normal(n)
+    mixed = np.where(rng.random(n) < 0.5, 1e30, 1e-30).astype(np.float32) * np.sign(rng.standard_normal(n))
+    mixed = mixed.astype(np.float32)
+    ints = rng.integers(-1000, 1000, n).astype(np.float32)
+    zeros = np.full(n, -0.0, np.float32)
+    infs = walk.copy()
+    infs[n // 3] = np.inf
+    infs[n // 3 + 5] = -np.inf
+    infs[2 * n // 3] = np.inf
+    halves = S.walk(n, np.float16, seed=seed + 1)
+    return {"walk": walk, "noise64": noise, "mixed": mixed, "ints": ints, "zeros": zeros, "infs": infs,
+            "halves": halves}
+
+
+@pytest.mark.parametrize("n,n_out", [(2_000_003, 60), (3_000_017, 1000), (1_300_021, 5)])
+def test_lttb_long_bucket_centres_bit_exact(ts, oracle_mod, n, n_out):
+    """Centres of long buckets (a workgroup per bucket, tile summaries folded
+    into the sequential sum where no rounding can occur, point by point where
+    it can): bit-identical to the oracle's index-order double sums, signed
+    zeros and NaN included, with and without float x; buckets of ~33k, ~3k
+    and ~433k points (several rounds of tile summaries)."""
+    rng = np.random.default_rng(n)
+    xs = {"none": None, "f64": S.timestamps(n, 10, seed=n).astype(np.float64),
+          "f32": (np.cumsum(rng.integers(1, 4, n)) * 0.125).astype(np.float32)}
+    for name, y in _centre_cases(n, seed=n % 1000).items():
+        for xn, xx in xs.items():
+            say(f"[centres] n={n} n_out={n_out} y={name} x={xn}")
+            cx, cy = ts.lttb_centres(dev(y), n_out, None if xx is None else dev(xx))
+            ecx, ecy = oracle_mod.lttb_centres(y, n_out, x=xx)
+            assert _bits_equal(cy.cpu().numpy(), ecy), (name, xn)
+            assert _bits_equal(cx.cpu().numpy(), ecx), (name, xn)
+        if name in ("walk", "noise64", "mixed"):
+            say(f"[centres] lttb n={n} n_out={n_out} y={name}")
+            assert np.array_equal(gpu(ts, "lttb", y, n_out), oracle_mod.lttb(y, n_out))
+
+
 # ------------------------------------------------------------------ errors
 
 
