@@ -30,6 +30,10 @@ namespace {
 
 const int64_t kMinChunk = 4096;
 const int64_t kStageBin = 4096, kStageChunk = 8192;
+// Tasks without x whose bins hold 4..512 KB of y: one wavefront per bin (the
+// single-series rule, also for bins of fewer than kStageBin elements), no
+// chunks and no merge.
+const int64_t kDirectMinBinBytes = 4096, kDirectMaxBinBytes = 512 << 10;
 
 size_t esize(int dt) { return elem_size(dt); }
 
@@ -49,6 +53,7 @@ size_t batch_layout(ts_plan *p, int64_t chunk_bytes) {
     p->group_cb[g].clear();
     p->group_tix[g].clear();
     p->group_total[g] = 0;
+    p->group_bytes[g] = 0;
   }
   size_t o = 0;
   int64_t ti = 0;
@@ -92,8 +97,10 @@ size_t batch_layout(ts_plan *p, int64_t chunk_bytes) {
       // bins averaging fewer than kStageBin elements: LDS-staged chunks
       // (the NaN-aware scan has no staged form)
       t.stage = !nan_task && t.n / t.nb < kStageBin ? 1 : 0;
-      t.chunk = (t.stage ? kStageChunk : chunk_bytes) / es;
-      grp = nan_task ? 22 + t.ydt : t.ydt + 11 * t.stage;
+      const int64_t bin_bytes = t.n / t.nb * es;
+      if (!nan_task && !t.x && bin_bytes >= kDirectMinBinBytes && bin_bytes <= kDirectMaxBinBytes) t.stage = 2;
+      t.chunk = (t.stage == 1 ? kStageChunk : chunk_bytes) / es;
+      grp = nan_task ? 22 + t.ydt : t.stage == 2 ? kBatchDirectGroup + t.ydt : t.ydt + 11 * t.stage;
       t.chunk_begin = p->group_total[grp];
       t.shift = (int64_t)(((uintptr_t)t.y & 15) / (uintptr_t)es);
       t.nchunks = (t.n + t.shift + t.chunk - 1) / t.chunk;
@@ -116,7 +123,9 @@ size_t batch_layout(ts_plan *p, int64_t chunk_bytes) {
       o = al256(o + 8 * (size_t)t.nb);
       p->group_cb[grp].push_back(p->group_total[grp]);
       p->group_tix[grp].push_back((int32_t)ti);
-      p->group_total[grp] += t.nchunks;
+      // a direct task's work items are its bins
+      p->group_total[grp] += t.stage == 2 ? t.nb : t.nchunks;
+      p->group_bytes[grp] += (double)t.n * (double)es;
       p->total_chunks += t.nchunks;
       p->total_slots += t.nb + 1;
     }
@@ -246,13 +255,16 @@ int tsds::batch_enqueue(const ts_plan *p, const void *d_table, int64_t *out, int
   // Groups by estimated cost, largest first, each onto the stream with the
   // least cost so far (longest-processing-time first).  Cost = the group's
   // bytes weighted by how slowly its kernel moves them: staged groups (many
-  // small bins, latency-bound) x4, bytes x3, 16-bit types x1.5 (measured on
-  // the 512-series mix: 0.687 -> 0.640 ms against bytes-only ordering).
+  // small bins, latency-bound) x4; chunked scans of bytes x3, of 16-bit
+  // types x1.5 (measured on the 512-series mix: 0.687 -> 0.640 ms against
+  // bytes-only ordering); groups reduced a wavefront per bin x1, bytes x4
+  // (alone on the GPU the byte group moves ~1.7 TB/s where the others move
+  // ~5: its fold keeps four wavefronts per SIMD), so that it starts first.
   auto cost = [p](int g) {
-    const bool staged = g < 22 && g / 11 == 1;
-    const double bytes = (double)p->group_total[g] * (double)(staged ? kStageChunk : p->chunk_bytes);
+    const bool staged = g < 22 && g / 11 == 1, direct = g >= kBatchDirectGroup;
     const size_t es = esize(g % 11);
-    return bytes * (staged ? 4.0 : es == 1 ? 3.0 : es == 2 ? 1.5 : 1.0);
+    if (direct) return p->group_bytes[g] * (es == 1 ? 4.0 : 1.0);
+    return p->group_bytes[g] * (staged ? 4.0 : es == 1 ? 3.0 : es == 2 ? 1.5 : 1.0);
   };
   std::vector<int> order;
   for (int g = 0; g < kBatchGroups; g++)
@@ -286,8 +298,8 @@ int tsds::batch_enqueue(const ts_plan *p, const void *d_table, int64_t *out, int
     bg.ntasks = (int64_t)p->group_cb[g].size();
     bg.total = p->group_total[g];
     bg.ydt = g % 11;
-    bg.nan = g >= 22 ? 1 : 0;
-    bg.stage = g >= 22 ? 0 : g / 11;
+    bg.nan = g >= 22 && g < kBatchDirectGroup ? 1 : 0;
+    bg.stage = g >= kBatchDirectGroup ? 2 : g >= 22 ? 0 : g / 11;
     const hipStream_t s = queue_of[k] > 0 ? p->side[queue_of[k] - 1] : st;
     if ((e = launch_batch_scan(a, bg, p->grid_blocks, s)) != hipSuccess)
       return api_fail(TS_ERR_HIP, "batch scan launch failed");

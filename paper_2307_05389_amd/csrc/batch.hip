@@ -122,9 +122,64 @@ __global__ __launch_bounds__(256) void k_batch_scan_staged(const BatchTask *__re
   }
 }
 
+__device__ inline MergeParams task_merge_params(const BatchArgs &a, const BatchTask &t);
+
+// A group of tasks of one element type reduced one wavefront per bin (no
+// chunks, no partials, no merge): work item = bin; the wavefront finds its
+// task, reduces the whole bin with the single-series tile fold and writes the
+// bin's selection.  (One launch for every type, with a wave-uniform type
+// switch, sized every wavefront for the widest fold: 159 VGPRs, three
+// wavefronts per SIMD.)
+template <typename T, int U, int NB>
+__global__ __launch_bounds__(256) void k_batch_direct(BatchArgs a, const int64_t *__restrict__ cb,
+                                                      const int32_t *__restrict__ tix, int64_t ntasks, int64_t total) {
+  const int lane = lane_id();
+  const int64_t item = uniform((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6));
+  if (item >= total) return;
+  const int64_t k = uniform(group_pos_of_item(cb, ntasks, item, lane));
+  const BatchTask &t = a.tasks[uniform(tix[k])];
+  const int64_t bin = item - uniform(t.chunk_begin);
+  const MergeParams mp = task_merge_params(a, t);
+  int64_t s, e;
+  bin_range(mp, bin, s, e);
+  if (s >= e) {
+    if (lane == 0) mp.cnt[bin] = 0;
+    return;
+  }
+  const u32x4 *__restrict__ base = (const u32x4 *)((const T *)t.y - t.shift);
+  u32x4 buf[NB][U];
+  SegState<typename Elem<T>::C> st;
+  wave_segment<T, U, NB>(base, t.shift, s, e, lane, buf, 0, st);
+  if (lane == 0) mp.cnt[bin] = bin_selection(s, e, st.imn, st.imx, mp.m4, mp.sel + 4 * bin);
+}
+
+static hipError_t launch_batch_direct(const BatchArgs &a, const BatchGroup &g, hipStream_t st) {
+  const dim3 grid((unsigned)((g.total + 3) / 4)), block(256);
+#define TSDS_DIRECT_ARGS a, g.cb, g.tix, g.ntasks, g.total
+  // tile shapes of the single-series per-bin kernel (one- and two-byte types
+  // 4x1, wider types 4x2)
+  switch (g.ydt) {
+    case TS_I8: k_batch_direct<int8_t, 4, 1><<<grid, block, 0, st>>>(TSDS_DIRECT_ARGS); break;
+    case TS_I16: k_batch_direct<int16_t, 4, 1><<<grid, block, 0, st>>>(TSDS_DIRECT_ARGS); break;
+    case TS_I32: k_batch_direct<int32_t, 4, 2><<<grid, block, 0, st>>>(TSDS_DIRECT_ARGS); break;
+    case TS_I64: k_batch_direct<int64_t, 4, 2><<<grid, block, 0, st>>>(TSDS_DIRECT_ARGS); break;
+    case TS_U8: k_batch_direct<uint8_t, 4, 1><<<grid, block, 0, st>>>(TSDS_DIRECT_ARGS); break;
+    case TS_U16: k_batch_direct<uint16_t, 4, 1><<<grid, block, 0, st>>>(TSDS_DIRECT_ARGS); break;
+    case TS_U32: k_batch_direct<uint32_t, 4, 2><<<grid, block, 0, st>>>(TSDS_DIRECT_ARGS); break;
+    case TS_U64: k_batch_direct<uint64_t, 4, 2><<<grid, block, 0, st>>>(TSDS_DIRECT_ARGS); break;
+    case TS_F16: k_batch_direct<half_t, 4, 1><<<grid, block, 0, st>>>(TSDS_DIRECT_ARGS); break;
+    case TS_F32: k_batch_direct<float, 4, 2><<<grid, block, 0, st>>>(TSDS_DIRECT_ARGS); break;
+    case TS_F64: k_batch_direct<double, 4, 2><<<grid, block, 0, st>>>(TSDS_DIRECT_ARGS); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef TSDS_DIRECT_ARGS
+  return hipGetLastError();
+}
+
 hipError_t launch_batch_scan(const BatchArgs &a, const BatchGroup &g, int64_t grid_blocks, hipStream_t st) {
   if (g.nan) return launch_batch_scan_nan(a, g, grid_blocks, st);
   if (g.total == 0) return hipSuccess;
+  if (g.stage == 2) return launch_batch_direct(a, g, st);
   int64_t gb = grid_blocks;
   if (gb > (g.total + 3) / 4) gb = (g.total + 3) / 4;
   if (gb < 1) gb = 1;
@@ -197,7 +252,7 @@ __global__ __launch_bounds__(256) void k_batch_merge(BatchArgs a) {
   if (slot >= a.wave_slots) return;
   const BatchTask &t = a.tasks[a.slot_task[slot]];
   const int64_t bin = slot - t.slot_begin;
-  if (t.mode != 0 || bin >= t.nb) return;
+  if (t.mode != 0 || t.stage == 2 || bin >= t.nb) return;
   const MergeParams mp = task_merge_params(a, t);
   int64_t s, e;
   bin_range(mp, bin, s, e);
@@ -217,7 +272,7 @@ __global__ __launch_bounds__(256) void k_batch_merge_lanes(BatchArgs a) {
   if (slot >= a.total_slots) return;
   const BatchTask &t = a.tasks[a.slot_task[slot]];
   const int64_t bin = slot - t.slot_begin;
-  if (t.mode != 0 || bin >= t.nb) return;
+  if (t.mode != 0 || t.stage == 2 || bin >= t.nb) return;
   const MergeParams mp = task_merge_params(a, t);
   int64_t s, e;
   bin_range(mp, bin, s, e);

@@ -11,8 +11,10 @@
 #include "tsds.h"
 
 // Work-list groups: g = dtype + 11 * staged for the plain scan, 22 + dtype
-// for NaN-aware tasks (floating-point y only).
-constexpr int kBatchGroups = 33;
+// for NaN-aware tasks (floating-point y only), 33 + dtype for tasks reduced
+// one wavefront per bin (work items are bins, not chunks).
+constexpr int kBatchGroups = 44;
+constexpr int kBatchDirectGroup = 33;
 
 struct ts_plan {
   std::vector<ts_task> in;
@@ -24,6 +26,7 @@ struct ts_plan {
   std::vector<int64_t> group_cb[kBatchGroups];
   std::vector<int32_t> group_tix[kBatchGroups];
   int64_t group_total[kBatchGroups] = {0};
+  double group_bytes[kBatchGroups] = {0};  // bytes of y the group reads
   size_t group_off_cb[kBatchGroups] = {0}, group_off_tix[kBatchGroups] = {0};
   size_t ws_bytes = 0;      // for the largest chunk count in the tuning space
   int64_t out_needed = 0;   // max(out_offset + n_out)

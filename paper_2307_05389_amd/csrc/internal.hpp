@@ -160,10 +160,10 @@ struct BatchTask {
   int32_t ydt, xdt;
   int32_t algo;         // TS_MINMAX, TS_M4, TS_MINMAXLTTB, TS_NAN_MINMAX, TS_NAN_M4 (NaN-aware only for float y)
   int32_t mode;         // 0: scan; 1: n <= n_out (all indices); 2: MinMaxLTTB without preselection
-  int32_t stage;        // 1: staged chunks (many small bins)
+  int32_t stage;        // 1: staged chunks (many small bins); 2: a wavefront per bin (no chunks, no merge)
   int32_t pad_;
   int64_t shift, chunk, nchunks, nb;
-  int64_t chunk_begin;  // first work item (chunk) of this task in its dtype group's list
+  int64_t chunk_begin;  // first work item (chunk, or bin when stage == 2) of this task in its group's list
   int64_t slot_begin;   // first global bin slot (nb + 1 slots per task)
   int64_t n_out, out_offset;
   int64_t o_edges, o_binres, o_partL, o_partR, o_sel, o_cnt;

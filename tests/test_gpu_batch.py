@@ -144,3 +144,52 @@ def test_batch_walk_maps_beyond_64k_lds(ts, oracle_mod):
                     plain = ts.minmaxlttb(d["y"], s["n_out"], x=d["x"], minmax_ratio=s["minmax_ratio"])
                     assert np.array_equal(res[i], plain.cpu().numpy()), i
         b.close()
+
+
+def test_batch_direct_bins(ts, oracle_mod):
+    """Tasks without x whose bins hold 4..512 KB of y are reduced one
+    wavefront per bin (no chunks, no merge), beside chunked and staged tasks
+    and tasks with x in the same batch: every dtype, MinMax, M4 and the
+    MinMaxLTTB preselection, bins around both size limits, series off the
+    16-byte grid; equal to the oracle and to plain calls, graph replays
+    included."""
+    rng = np.random.default_rng(91)
+    dts = [np.float32, np.float16, np.int16, np.uint8, np.float64, np.int8, np.uint64, np.int32]
+    specs = []
+    for i, dt in enumerate(dts):
+        es = np.dtype(dt).itemsize
+        for bin_bytes in (4096, 20_000, 500_000):
+            algo = ["minmax", "m4", "minmaxlttb"][(i + bin_bytes) % 3]
+            L = int(rng.integers(1_000_000, 3_000_000)) // es
+            per = {"minmax": 2, "m4": 4, "minmaxlttb": 1}[algo]
+            ratio = 2
+            nb = max(1, L * es // bin_bytes)
+            n_out = per * nb if algo != "minmaxlttb" else max(3, nb)
+            y = S.walk(L + 3, dt, seed=300 + 3 * i + bin_bytes % 7)[3:]   # off the 16-byte grid
+            specs.append(dict(algo=algo, y=y, x=None, n_out=n_out, minmax_ratio=ratio))
+    # neighbours on the other paths: x, staged (short bins), chunked (long bins)
+    specs.append(dict(algo="m4", y=S.walk(400_000, np.float32, 401), x=S.timestamps(400_000, 20, seed=402),
+                      n_out=400, minmax_ratio=4))
+    specs.append(dict(algo="minmax", y=S.walk(300_000, np.int16, 403), x=None, n_out=20_000, minmax_ratio=4))
+    specs.append(dict(algo="minmax", y=S.walk(3_000_000, np.float32, 404), x=None, n_out=8, minmax_ratio=4))
+    dev = to_dev(specs)
+    b = ts.Batch(dev)
+    b.run()
+    res = [r.cpu().numpy() for r in b.results()]
+    for i, (s, d) in enumerate(zip(specs, dev)):
+        say(f"[batch direct] task {i} {s['algo']} {s['y'].dtype} n={len(s['y'])} n_out={s['n_out']}")
+        assert np.array_equal(res[i], oracle_of(oracle_mod, s)), i
+        if s["algo"] == "minmaxlttb":
+            plain = ts.minmaxlttb(d["y"], s["n_out"], x=d["x"], minmax_ratio=s["minmax_ratio"])
+        else:
+            plain = getattr(ts, s["algo"])(d["y"], s["n_out"], x=d["x"])
+        assert np.array_equal(res[i], plain.cpu().numpy()), i
+    ref = [r.cpu().clone() for r in b.results()]
+    for rep in range(3):
+        say(f"[batch direct] graph replay {rep}")
+        b.out.fill_(-1)
+        b.counts.fill_(-1)
+        b.run(graph=True)
+        torch.cuda.synchronize()
+        assert all(torch.equal(a, c.cpu()) for a, c in zip(ref, b.results())), rep
+    b.close()
