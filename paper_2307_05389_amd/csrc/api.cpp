@@ -498,6 +498,35 @@ static MmlPlan mml_plan(const ts_series &s, int64_t n_out, int64_t ratio) {
   return p;
 }
 
+// A side stream (default priority) and fork/join events per host thread and
+// device, created on first use: the LTTB centres of a plain series run there
+// beside the hull kernel (the hulls use the VALU and most of the LDS, the
+// centres stream the series from HBM; neither reads the other's output).
+struct SideStream {
+  hipStream_t s = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+  bool tried = false;
+};
+static thread_local SideStream g_side[64];
+
+static SideStream *side_stream(hipStream_t st) {
+  int dev = -1;
+  if ((st ? hipStreamGetDevice(st, &dev) : hipGetDevice(&dev)) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+  SideStream &ss = g_side[dev];
+  if (!ss.tried) {
+    ss.tried = true;
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) return nullptr;
+    if (cur != dev && hipSetDevice(dev) != hipSuccess) return nullptr;
+    const bool ok = hipStreamCreateWithFlags(&ss.s, hipStreamNonBlocking) == hipSuccess &&
+                    hipEventCreateWithFlags(&ss.fork, hipEventDisableTiming) == hipSuccess &&
+                    hipEventCreateWithFlags(&ss.join, hipEventDisableTiming) == hipSuccess;
+    if (cur != dev) (void)hipSetDevice(cur);
+    if (!ok) ss.s = nullptr;
+  }
+  return ss.s ? &ss : nullptr;
+}
+
 // Average candidates per bucket up to which the small-bucket map computes its
 // own centres (each anchor then re-reads at most a few points).
 static const int64_t kOwnCentresPerBucket = 8;
@@ -541,11 +570,20 @@ static int run_lttb(const ts_series &s, const int64_t *sel, int64_t m, const int
     p.gy = (uint64_t *)wsp(ws, lp.off_gy);
     if ((e = launch_lttb_gather(p, st)) != hipSuccess) return hip_fail(e, "lttb candidate gather");
   }
-  if (!own && (e = launch_lttb_centres(p, st)) != hipSuccess) return hip_fail(e, "lttb centres");
+  SideStream *ss = lp.mode == kLttbHull ? side_stream(st) : nullptr;
+  if (ss) {  // centres on the side stream, beside the hulls
+    if ((e = hipEventRecord(ss->fork, st)) != hipSuccess || (e = hipStreamWaitEvent(ss->s, ss->fork, 0)) != hipSuccess)
+      return hip_fail(e, "lttb fork");
+    if ((e = launch_lttb_centres(p, ss->s)) != hipSuccess) return hip_fail(e, "lttb centres");
+    if ((e = hipEventRecord(ss->join, ss->s)) != hipSuccess) return hip_fail(e, "lttb join");
+  } else if (!own && (e = launch_lttb_centres(p, st)) != hipSuccess) {
+    return hip_fail(e, "lttb centres");
+  }
   switch (lp.mode) {
     case kLttbSmall: e = launch_lttb_small(p, own, st); break;
     case kLttbHull:
       if ((e = launch_lttb_hull(p, st)) != hipSuccess) return hip_fail(e, "lttb hulls");
+      if (ss && (e = hipStreamWaitEvent(st, ss->join, 0)) != hipSuccess) return hip_fail(e, "lttb join");
       e = launch_lttb_hull_walk(p, st);
       break;
     default: e = launch_lttb_seq(p, st); break;
