@@ -514,6 +514,10 @@ static SideStream *side_stream(hipStream_t st) {
   if ((st ? hipStreamGetDevice(st, &dev) : hipGetDevice(&dev)) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
   SideStream &ss = g_side[dev];
   if (!ss.tried) {
+    // not created while the caller's stream is being captured (stream
+    // creation is not a capturable operation); later calls create it
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (st && (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)) return nullptr;
     ss.tried = true;
     int cur = -1;
     if (hipGetDevice(&cur) != hipSuccess) return nullptr;

@@ -536,3 +536,37 @@ def test_error_paths(ts):
         ts.downsample_into("m4", y, 100, out, cnt, workspace=small_ws)
     torch.cuda.synchronize()
     assert bool((out == -7).all())
+
+
+def test_lttb_in_a_captured_graph(ts, oracle_mod):
+    """Plain LTTB with long buckets forks its centres onto a side stream and
+    joins them back; captured in a graph (first call inside the capture, and
+    after an eager call created the side stream) every replay equals the
+    eager result and the oracle, with eager work and synchronisation between
+    replays."""
+    n, n_out = 3_000_017, 200
+    y = S.walk(n, np.float32, seed=95)
+    yd = dev(y)
+    want = oracle_mod.lttb(y, n_out)
+    for eager_first in (False, True):
+        out = torch.full((n_out,), -1, dtype=torch.int64, device="cuda")
+        cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+        need = ts.workspace_bytes("lttb", yd, n_out)
+        ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+        side = torch.cuda.Stream()
+        if eager_first:
+            with torch.cuda.stream(side):
+                ts.downsample_into("lttb", yd, n_out, out, cnt, workspace=ws)
+            torch.cuda.synchronize()
+            assert np.array_equal(out[: int(cnt.item())].cpu().numpy(), want)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=side):
+            ts.downsample_into("lttb", yd, n_out, out, cnt, workspace=ws, stream=torch.cuda.current_stream())
+        for rep in range(3):
+            say(f"[lttb graph] eager_first={eager_first} replay {rep}")
+            out.fill_(-1)
+            g.replay()
+            torch.cuda.synchronize()
+            assert int(cnt.item()) == n_out and np.array_equal(out.cpu().numpy(), want), rep
+            junk = torch.randn(1 << 20, device="cuda").sum()
+            del junk
