@@ -102,14 +102,17 @@ static const int64_t kDirectWideMinBins = 2048, kDirectWideMinBinBytes = 4096, k
 static const int64_t kDirectMaxBinCount = (int64_t)1 << 25;
 
 // Tile shape of the per-bin kernel (the scan's variant numbering: 0 = 4x2,
-// 1 = 4x1, 2 = 8x1, 3 = 2x2) from the same sweeps: bins under 8 KB take
-// small tiles two in flight; one- and two-byte types 4x1 (their fold needs
-// the most registers: 4x2 halves the wavefronts per SIMD); four- and
-// eight-byte types 4x2, 8x1 from 32 KB bins.
+// 1 = 4x1, 2 = 8x1, 3 = 2x2) from the same sweeps: bytes 4x1 (their fold
+// spreads every byte into a 16-bit lane: with two tiles in flight the
+// registers allow three wavefronts per SIMD instead of eight), two-byte
+// types 4x2, four- and eight-byte types 2x2 under 8 KB bins, else 4x2, and
+// eight-byte types 8x1 from 32 KB bins.
 static int32_t direct_variant(int ydt, int64_t bin_bytes) {
+  const int64_t es = (int64_t)elem_size(ydt);
+  if (es == 1) return 1;
+  if (es == 2) return 0;
   if (bin_bytes < 8192) return 3;
-  if (elem_size(ydt) <= 2) return 1;
-  return bin_bytes >= 32768 ? 2 : 0;
+  return es == 8 && bin_bytes >= 32768 ? 2 : 0;
 }
 
 static bool direct_bins(int ydt, bool has_x, int64_t n, int64_t nb) {

@@ -123,6 +123,7 @@ __global__ __launch_bounds__(256) void k_batch_scan_staged(const BatchTask *__re
 }
 
 __device__ inline MergeParams task_merge_params(const BatchArgs &a, const BatchTask &t);
+__device__ inline MergeParams task_merge_params_uniform(const BatchArgs &a, const BatchTask *__restrict__ t);
 
 // A group of tasks of one element type reduced one wavefront per bin (no
 // chunks, no partials, no merge): work item = bin; the wavefront finds its
@@ -137,37 +138,37 @@ __global__ __launch_bounds__(256) void k_batch_direct(BatchArgs a, const int64_t
   const int64_t item = uniform((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6));
   if (item >= total) return;
   const int64_t k = uniform(group_pos_of_item(cb, ntasks, item, lane));
-  const BatchTask &t = a.tasks[uniform(tix[k])];
-  const int64_t bin = item - uniform(t.chunk_begin);
-  const MergeParams mp = task_merge_params(a, t);
+  const BatchTask *tk = a.tasks + uniform(tix[k]);
+  const int64_t bin = item - uniform(tk->chunk_begin);
+  const MergeParams mp = task_merge_params_uniform(a, tk);
   int64_t s, e;
   bin_range(mp, bin, s, e);
   if (s >= e) {
     if (lane == 0) mp.cnt[bin] = 0;
     return;
   }
-  const u32x4 *__restrict__ base = (const u32x4 *)((const T *)t.y - t.shift);
+  const u32x4 *__restrict__ base = (const u32x4 *)((const T *)uniform(tk->y) - mp.shift);
   u32x4 buf[NB][U];
   SegState<typename Elem<T>::C> st;
-  wave_segment<T, U, NB>(base, t.shift, s, e, lane, buf, 0, st);
+  wave_segment<T, U, NB>(base, mp.shift, s, e, lane, buf, 0, st);
   if (lane == 0) mp.cnt[bin] = bin_selection(s, e, st.imn, st.imx, mp.m4, mp.sel + 4 * bin);
 }
 
 static hipError_t launch_batch_direct(const BatchArgs &a, const BatchGroup &g, hipStream_t st) {
   const dim3 grid((unsigned)((g.total + 3) / 4)), block(256);
 #define TSDS_DIRECT_ARGS a, g.cb, g.tix, g.ntasks, g.total
-  // tile shapes of the single-series per-bin kernel (one- and two-byte types
-  // 4x1, wider types 4x2)
+  // tile shapes of the single-series per-bin kernel (bytes 4x1, wider types
+  // 4x2)
   switch (g.ydt) {
     case TS_I8: k_batch_direct<int8_t, 4, 1><<<grid, block, 0, st>>>(TSDS_DIRECT_ARGS); break;
-    case TS_I16: k_batch_direct<int16_t, 4, 1><<<grid, block, 0, st>>>(TSDS_DIRECT_ARGS); break;
+    case TS_I16: k_batch_direct<int16_t, 4, 2><<<grid, block, 0, st>>>(TSDS_DIRECT_ARGS); break;
     case TS_I32: k_batch_direct<int32_t, 4, 2><<<grid, block, 0, st>>>(TSDS_DIRECT_ARGS); break;
     case TS_I64: k_batch_direct<int64_t, 4, 2><<<grid, block, 0, st>>>(TSDS_DIRECT_ARGS); break;
     case TS_U8: k_batch_direct<uint8_t, 4, 1><<<grid, block, 0, st>>>(TSDS_DIRECT_ARGS); break;
-    case TS_U16: k_batch_direct<uint16_t, 4, 1><<<grid, block, 0, st>>>(TSDS_DIRECT_ARGS); break;
+    case TS_U16: k_batch_direct<uint16_t, 4, 2><<<grid, block, 0, st>>>(TSDS_DIRECT_ARGS); break;
     case TS_U32: k_batch_direct<uint32_t, 4, 2><<<grid, block, 0, st>>>(TSDS_DIRECT_ARGS); break;
     case TS_U64: k_batch_direct<uint64_t, 4, 2><<<grid, block, 0, st>>>(TSDS_DIRECT_ARGS); break;
-    case TS_F16: k_batch_direct<half_t, 4, 1><<<grid, block, 0, st>>>(TSDS_DIRECT_ARGS); break;
+    case TS_F16: k_batch_direct<half_t, 4, 2><<<grid, block, 0, st>>>(TSDS_DIRECT_ARGS); break;
     case TS_F32: k_batch_direct<float, 4, 2><<<grid, block, 0, st>>>(TSDS_DIRECT_ARGS); break;
     case TS_F64: k_batch_direct<double, 4, 2><<<grid, block, 0, st>>>(TSDS_DIRECT_ARGS); break;
     default: return hipErrorInvalidValue;
@@ -240,6 +241,25 @@ __device__ inline MergeParams task_merge_params(const BatchArgs &a, const BatchT
   mp.m4 = t.algo == TS_M4 || t.algo == TS_NAN_M4;
   mp.sel = (int64_t *)(a.ws + t.o_sel);
   mp.cnt = (int64_t *)(a.ws + t.o_cnt);
+  return mp;
+}
+
+// The same with every field read as wave-uniform (scalar registers), for a
+// task pointer that is itself wave-uniform.
+__device__ inline MergeParams task_merge_params_uniform(const BatchArgs &a, const BatchTask *__restrict__ t) {
+  MergeParams mp;
+  mp.n = uniform(t->n);
+  mp.shift = uniform(t->shift);
+  mp.chunk = uniform(t->chunk);
+  mp.edges = uniform(t->x) ? (const int64_t *)(a.ws + uniform(t->o_edges)) : nullptr;
+  mp.nb = uniform(t->nb);
+  mp.binres = (const int64_t *)(a.ws + uniform(t->o_binres));
+  mp.partL = (const Partial *)(a.ws + uniform(t->o_partL));
+  mp.partR = (const Partial *)(a.ws + uniform(t->o_partR));
+  const int32_t algo = uniform(t->algo);
+  mp.m4 = algo == TS_M4 || algo == TS_NAN_M4;
+  mp.sel = (int64_t *)(a.ws + uniform(t->o_sel));
+  mp.cnt = (int64_t *)(a.ws + uniform(t->o_cnt));
   return mp;
 }
 

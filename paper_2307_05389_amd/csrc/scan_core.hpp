@@ -332,11 +332,15 @@ __device__ inline void vec_minmax_masked(const u32x4 &d, uint32_t q0, uint32_t r
                                          typename Elem<T>::C &mn, typename Elem<T>::C &mx) {
   using E = Elem<T>;
   constexpr int VEC = 16 / (int)sizeof(T);
+  // valid j in [a, b): bounds relative to the vector, so that each test is
+  // against an immediate j (absolute positions q0 + j would be hoisted out
+  // of the tile loop as VEC registers per vector)
+  const int a = (int)rlo - (int)q0, b = (int)rhi - (int)q0;
   mn = E::highest();
   mx = E::lowest();
 #pragma unroll
   for (int j = 0; j < VEC; j++) {
-    const bool ok = q0 + j >= rlo && q0 + j < rhi;
+    const bool ok = j >= a && j < b;
     const typename E::C v = extract<T>(d, j);
     mn = vmin(mn, ok ? v : E::highest());
     mx = vmax(mx, ok ? v : E::lowest());
@@ -346,10 +350,11 @@ template <typename T>
 __device__ inline int vec_first_masked(const u32x4 &d, typename Elem<T>::C target, uint32_t q0, uint32_t rlo,
                                        uint32_t rhi) {
   constexpr int VEC = 16 / (int)sizeof(T);
+  const int a = (int)rlo - (int)q0, b = (int)rhi - (int)q0;
   int r = VEC;
 #pragma unroll
   for (int j = VEC - 1; j >= 0; j--)
-    if (q0 + j >= rlo && q0 + j < rhi && extract<T>(d, j) == target) r = j;
+    if (j >= a && j < b && extract<T>(d, j) == target) r = j;
   return r;
 }
 
@@ -426,9 +431,18 @@ __device__ inline void fold_tile(const u32x4 (&d)[U], int64_t vt, int64_t shift,
 #pragma unroll
     for (int u = 0; u < U; u++) VecOps<T>::minmax(d[u], vm[u], vx[u]);
   } else {
+    // A segment end cuts at most two vectors of the tile: every other vector
+    // is wholly inside (reduced as in a full tile) or wholly outside
+    // (neutral); only a cut vector is reduced element by element.
 #pragma unroll
-    for (int u = 0; u < U; u++)
-      vec_minmax_masked<T>(d[u], (uint32_t)((u * kWave + lane) * VEC), rlo, rhi, vm[u], vx[u]);
+    for (int u = 0; u < U; u++) {
+      const uint32_t q0 = (uint32_t)((u * kWave + lane) * VEC);
+      VecOps<T>::minmax(d[u], vm[u], vx[u]);
+      const bool out = q0 + VEC <= rlo || q0 >= rhi;
+      vm[u] = out ? E::highest() : vm[u];
+      vx[u] = out ? E::lowest() : vx[u];
+      if (!out && (q0 < rlo || q0 + VEC > rhi)) vec_minmax_masked<T>(d[u], q0, rlo, rhi, vm[u], vx[u]);
+    }
   }
   C tmn = vm[0], tmx = vx[0];
 #pragma unroll
