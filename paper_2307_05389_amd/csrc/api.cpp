@@ -70,7 +70,8 @@ static ScanShape default_shape(int ydt) {
   switch (ydt) {
     case TS_U8: return {1, 16384, 0, 0};
     case TS_I8: return {1, 16384, 0, 0};
-    case TS_I16: case TS_U16: case TS_F16: return {0, 16384, 0, 0};
+    case TS_I16: case TS_U16: return {0, 16384, 0, 0};
+    case TS_F16: return {2, 16384, 0, 0};
     case TS_I32: case TS_U32: case TS_F32: return {2, 16384, 0, 0};
     default: return {2, 16384, 0, 0};
   }
@@ -88,14 +89,18 @@ static int32_t g_direct_override = -1;
 // kDirectMinBins bins of at least kDirectMinBin elements (the call is
 // launch-bound there), and series without x (equal bins, so every wavefront
 // reads the same amount) in at least kDirectWideMinBins bins of
-// kDirectWideMinBinBytes..kDirectWideMaxBinBytes.  Sweeps of MinMax over 1 GB
-// series on MI355X (u8, i16, f16, f32, f64; bins of 5 KB to 1 MB): from 5 KB
-// to 333 KB bins the per-bin wavefront is the fastest path for every type
-// (10 KB u8 bins 3.2 -> 4.3 TB/s, 10 KB f32 bins 4.7 -> 6.0 TB/s); below
-// ~4 KB the LDS-staged chunks win, and with ~1,000 bins there are too few
-// wavefronts and the chunked scan wins.
+// kDirectWideMinBinBytes..kDirectWideMaxBinBytes (eight-byte types from
+// kDirectWideMinBins8 bins of at least kDirectWide8MinBinBytes).  Sweeps of
+// MinMax over 1 GB series on MI355X (u8, i16, f16, f32, f64; bins of 5 KB to
+// 1 MB): from 5 KB to 500 KB bins the per-bin wavefront is the fastest path
+// for every type (10 KB u8 bins 3.8 -> 5.7 TB/s, 10 KB f32 bins 4.8 -> 6.0
+// TB/s, 500 KB bins 5.7-6.1 -> 6.2-6.6 TB/s); below ~4 KB the LDS-staged
+// chunks win, and with 1,000 bins there are too few wavefronts and the
+// chunked scan wins (u8 3.9 against 6.0 TB/s), except for f64, whose fold is
+// the cheapest per byte (6.5 against 6.1 TB/s).
 static const int64_t kDirectMaxBytes = 8 << 20, kDirectMinBins = 64, kDirectMinBin = 256;
-static const int64_t kDirectWideMinBins = 2048, kDirectWideMinBinBytes = 4096, kDirectWideMaxBinBytes = 512 << 10;
+static const int64_t kDirectWideMinBins = 2000, kDirectWideMinBinBytes = 4096, kDirectWideMaxBinBytes = 512 << 10;
+static const int64_t kDirectWideMinBins8 = 1000, kDirectWide8MinBinBytes = 256 << 10;
 
 // The per-bin grid has 64 threads per bin: at most 2^25 bins keeps it within
 // 2^31 threads.
@@ -123,8 +128,9 @@ static bool direct_bins(int ydt, bool has_x, int64_t n, int64_t nb) {
   const int64_t es = (int64_t)elem_size(ydt);
   if (n * es <= kDirectMaxBytes && nb >= kDirectMinBins && n / nb >= kDirectMinBin) return true;
   const int64_t bin_bytes = n / nb * es;
-  return !has_x && nb >= kDirectWideMinBins && bin_bytes >= kDirectWideMinBinBytes &&
-         bin_bytes <= kDirectWideMaxBinBytes;
+  if (has_x || bin_bytes < kDirectWideMinBinBytes) return false;
+  if (es == 8 && nb >= kDirectWideMinBins8 && bin_bytes >= kDirectWide8MinBinBytes) return true;
+  return nb >= kDirectWideMinBins && bin_bytes <= kDirectWideMaxBinBytes;
 }
 
 // Bins averaging fewer than kStageBin elements go through LDS-staged chunks

@@ -205,19 +205,28 @@ def test_direct_bins(ts, oracle_mod, dtype):
                 _direct_cases(ts, oracle_mod, y, x, off, f"{np.dtype(dtype).name} variant={variant}")
     finally:
         ts.set_tuning()
-    # automatic choice: > 8 MB, no x, >= 2048 bins of 4-512 KB
+    # automatic choice: > 8 MB, no x, >= 2000 bins of 4-512 KB (eight-byte
+    # types also 1000 bins of >= 256 KB)
+    from paper_2307_05389_amd import _lib as L
     es = np.dtype(dtype).itemsize
     nbig = (16 << 20) // es + 13
     ybig = S.walk(nbig, dtype, seed=84)
     for bin_bytes in (4096, 5000, 8192):
         nb = nbig * es // bin_bytes
-        if nb < 2048:
+        if nb < 2000:
             continue
-        from paper_2307_05389_amd import _lib as L
         assert L.scan_config(dev(ybig[:8]).dtype, nbig, nb)[2].startswith("tsds::k_bins_direct<")
         for algo, per in (("minmax", 2), ("m4", 4)):
             say(f"[direct auto] {np.dtype(dtype).name} bin_bytes={bin_bytes} {algo}")
             assert np.array_equal(gpu(ts, algo, ybig, per * nb), orc(oracle_mod, algo, ybig, per * nb))
+    if es == 8:
+        n8 = 1000 * (1 << 15) + 7
+        y8 = S.walk(n8, dtype, seed=85)
+        assert L.scan_config(dev(y8[:8]).dtype, n8, 1000)[2].startswith("tsds::k_bins_direct<")
+        assert not L.scan_config(dev(y8[:8]).dtype, n8 // 2, 1000)[2].startswith("tsds::k_bins_direct<")
+        for algo, per in (("minmax", 2), ("m4", 4)):
+            say(f"[direct auto] {np.dtype(dtype).name} 1000 bins of 256 KB {algo}")
+            assert np.array_equal(gpu(ts, algo, y8, per * 1000), orc(oracle_mod, algo, y8, per * 1000))
 
 
 def x_patterns(n, seed):
