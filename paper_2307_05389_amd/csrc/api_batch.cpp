@@ -157,6 +157,21 @@ size_t batch_layout(ts_plan *p, int64_t chunk_bytes) {
     p->tasks.push_back(t);
     ti++;
   }
+  // Per-bin groups: longest bins first.  A wavefront reduces a whole bin, so
+  // the wavefronts of the longest bins set the group's time; started first,
+  // they overlap with the short ones instead of trailing after them.
+  for (int g = kBatchDirectGroup; g < kBatchGroups; g++) {
+    std::vector<int32_t> &tix = p->group_tix[g];
+    if (tix.size() < 2) continue;
+    const auto bin_len = [&](int32_t k) { return p->tasks[k].n / p->tasks[k].nb; };
+    std::stable_sort(tix.begin(), tix.end(), [&](int32_t a, int32_t b) { return bin_len(a) > bin_len(b); });
+    int64_t pos = 0;
+    for (size_t i = 0; i < tix.size(); i++) {
+      p->group_cb[g][i] = pos;
+      p->tasks[tix[i]].chunk_begin = pos;
+      pos += p->tasks[tix[i]].nb;
+    }
+  }
   // Bin slots: tasks whose bins span many chunks first (a wavefront merges
   // each of their bins), then the rest (a thread per bin).
   p->wave_slots = 0;

@@ -227,6 +227,38 @@ template <typename T> struct VecOps {
   }
 };
 
+// Bits [lo, hi) of a 64-bit word (bounds clamped to [0, 64]).
+__device__ inline uint64_t bit_range64(int lo, int hi) {
+  lo = lo < 0 ? 0 : lo > 64 ? 64 : lo;
+  hi = hi < 0 ? 0 : hi > 64 ? 64 : hi;
+  const uint64_t below_hi = hi >= 64 ? ~0ull : (1ull << hi) - 1;
+  const uint64_t below_lo = lo >= 64 ? ~0ull : (1ull << lo) - 1;
+  return below_hi & ~below_lo;
+}
+
+// First element j in [a, b) of a vector of B-bit lanes (B = 8 or 16) whose
+// bits, under magmask, equal the repeated pattern; 128 / B if none.  Each
+// dword takes the exact zero-lane test (7-bit sums: no borrow from one lane
+// into the next, so every lane's flag is exact, not only the lowest), the
+// flags of lanes outside [a, b) are cleared with a bit range over the two
+// 64-bit halves, and the lowest flag left is the answer.  Branch-free, with
+// no test per element.
+template <int B>
+__device__ inline int first_equal_in(const u32x4 &d, uint32_t pat, uint32_t magmask, int a, int b) {
+  constexpr uint32_t LOW = B == 8 ? 0x7f7f7f7fu : 0x7fff7fffu;
+  uint32_t z[4];
+#pragma unroll
+  for (int c = 0; c < 4; c++) {
+    const uint32_t t = (d[c] & magmask) ^ pat;
+    z[c] = ~(((t & LOW) + LOW) | t | LOW);  // top bit of a lane set iff the lane is zero
+  }
+  const uint64_t zlo = (uint64_t)z[1] << 32 | z[0], zhi = (uint64_t)z[3] << 32 | z[2];
+  const uint64_t mlo = zlo & bit_range64(a * B, b * B), mhi = zhi & bit_range64(a * B - 64, b * B - 64);
+  if (mlo) return __builtin_ctzll(mlo) / B;
+  if (mhi) return (64 + __builtin_ctzll(mhi)) / B;
+  return 128 / B;
+}
+
 template <typename V>
 __device__ inline void pk_vec_minmax(const u32x4 &d, V &a, V &b) {
   a = as2<V>(d.x);
@@ -315,6 +347,9 @@ template <> struct VecOps<uint8_t> {
     byte_vec_minmax<0u>(d, mn, mx);
   }
   static __device__ inline int first(const u32x4 &d, uint32_t t) { return first8(d, t & 0xffu); }
+  static __device__ inline int first_in(const u32x4 &d, uint32_t t, int a, int b) {
+    return first_equal_in<8>(d, (t & 0xffu) * 0x01010101u, ~0u, a, b);
+  }
 };
 template <> struct VecOps<int8_t> {
   static __device__ inline void minmax(const u32x4 &d, int32_t &mn, int32_t &mx) {
@@ -324,17 +359,22 @@ template <> struct VecOps<int8_t> {
     mx = (int32_t)b - 128;
   }
   static __device__ inline int first(const u32x4 &d, int32_t t) { return first8(d, (uint32_t)t & 0xffu); }
+  static __device__ inline int first_in(const u32x4 &d, int32_t t, int a, int b) {
+    return first_equal_in<8>(d, ((uint32_t)t & 0xffu) * 0x01010101u, ~0u, a, b);
+  }
 };
 
 // Masked versions (segment ends): positions outside [rlo, rhi) are ignored.
+// Only a vector that a segment end cuts takes this path, at most two per
+// tile.  The bounds are made relative to the vector, so that each test
+// compares an immediate j (tests of absolute positions q0 + j depend only on
+// the lane, and the compiler would compute them all before the tile loop and
+// keep them in registers).
 template <typename T>
 __device__ inline void vec_minmax_masked(const u32x4 &d, uint32_t q0, uint32_t rlo, uint32_t rhi,
                                          typename Elem<T>::C &mn, typename Elem<T>::C &mx) {
   using E = Elem<T>;
   constexpr int VEC = 16 / (int)sizeof(T);
-  // valid j in [a, b): bounds relative to the vector, so that each test is
-  // against an immediate j (absolute positions q0 + j would be hoisted out
-  // of the tile loop as VEC registers per vector)
   const int a = (int)rlo - (int)q0, b = (int)rhi - (int)q0;
   mn = E::highest();
   mx = E::lowest();
@@ -346,16 +386,22 @@ __device__ inline void vec_minmax_masked(const u32x4 &d, uint32_t q0, uint32_t r
     mx = vmax(mx, ok ? v : E::lowest());
   }
 }
+// Bytes use the branch-free lane test (VecOps<T>::first_in); with sixteen
+// elements a test per element costs more instructions and registers.
 template <typename T>
 __device__ inline int vec_first_masked(const u32x4 &d, typename Elem<T>::C target, uint32_t q0, uint32_t rlo,
                                        uint32_t rhi) {
   constexpr int VEC = 16 / (int)sizeof(T);
   const int a = (int)rlo - (int)q0, b = (int)rhi - (int)q0;
-  int r = VEC;
+  if constexpr (VEC == 16) {
+    return VecOps<T>::first_in(d, target, a, b);
+  } else {
+    int r = VEC;
 #pragma unroll
-  for (int j = VEC - 1; j >= 0; j--)
-    if (j >= a && j < b && extract<T>(d, j) == target) r = j;
-  return r;
+    for (int j = VEC - 1; j >= 0; j--)
+      if (j >= a && j < b && extract<T>(d, j) == target) r = j;
+    return r;
+  }
 }
 
 // Running result of one bin segment (wave-uniform).
