@@ -94,8 +94,7 @@ __global__ __launch_bounds__(256) void k_batch_scan(const BatchTask *__restrict_
   const int64_t i0 = total * w / W, i1 = total * (w + 1) / W;
 #pragma nounroll
   for (int64_t item = i0; item < i1; item++) {
-    const int64_t k = uniform(group_pos_of_item(cb, ntasks, item, lane));
-    const BatchTask *tk = tasks + uniform(tix[k]);
+    const BatchTask *tk = tasks + group_task_of_item(cb, tix, ntasks, item, lane);
     const ScanParams sp = task_scan_params_uniform(ws, tk, small);
     scan_chunk<T, U, NB>(sp, item - uniform(tk->chunk_begin), lane);
   }
@@ -115,8 +114,7 @@ __global__ __launch_bounds__(256) void k_batch_scan_staged(const BatchTask *__re
   u32x4 *lds = stage_lds + (threadIdx.x >> 6) * lds_per;
 #pragma nounroll
   for (int64_t item = i0; item < i1; item++) {
-    const int64_t k = uniform(group_pos_of_item(cb, ntasks, item, lane));
-    const BatchTask *tk = tasks + uniform(tix[k]);
+    const BatchTask *tk = tasks + group_task_of_item(cb, tix, ntasks, item, lane);
     const ScanParams sp = task_scan_params_uniform(ws, tk, small);
     scan_chunk_staged<T>(sp, item - uniform(tk->chunk_begin), lane, lds);
   }
@@ -137,8 +135,7 @@ __global__ __launch_bounds__(256) void k_batch_direct(BatchArgs a, const int64_t
   const int lane = lane_id();
   const int64_t item = uniform((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6));
   if (item >= total) return;
-  const int64_t k = uniform(group_pos_of_item(cb, ntasks, item, lane));
-  const BatchTask *tk = a.tasks + uniform(tix[k]);
+  const BatchTask *tk = a.tasks + group_task_of_item(cb, tix, ntasks, item, lane);
   const int64_t bin = item - uniform(tk->chunk_begin);
   const MergeParams mp = task_merge_params_uniform(a, tk);
   int64_t s, e;

@@ -32,22 +32,29 @@ __device__ inline ScanParams task_scan_params_uniform(char *ws, const BatchTask 
   return sp;
 }
 
-// Position k in the group's task list of the last task whose first work item
-// is <= item (tasks without items share their successor's start).
-__device__ inline int64_t group_pos_of_item(const int64_t *__restrict__ cb, int64_t ntasks, int64_t item, int lane) {
+// Task (index into the task table) of a group's work item: the last task of
+// the group's list whose first item is <= item (tasks without items share
+// their successor's start).  A 64-wide probe of the list narrows the range
+// 64-fold per round; in the last round (step 1) the probe is exact, and the
+// lanes load the task indices beside the starts, so the answer comes from a
+// lane of that same round trip (one dependent load per round, none after).
+__device__ inline int32_t group_task_of_item(const int64_t *__restrict__ cb, const int32_t *__restrict__ tix,
+                                             int64_t ntasks, int64_t item, int lane) {
+  if (ntasks <= 1) return uniform(tix[0]);
   int64_t lo = 0, hi = ntasks;  // cb[lo] <= item < cb[hi]
-  while (hi - lo > 1) {
+  for (;;) {
     const int64_t step = (hi - lo + 63) / 64;
     const int64_t q = lo + (int64_t)lane * step;
     const bool le = q < hi && cb[q] <= item;
-    const int cnt = __builtin_popcountll(ballot(le));
+    int32_t tq = 0;
+    if (step == 1 && q < hi) tq = tix[q];
+    const int cnt = __builtin_popcountll(ballot(le));  // >= 1: lane 0 probes lo
+    if (step == 1) return uniform(__builtin_amdgcn_readlane(tq, cnt - 1));
     const int64_t nlo = lo + (int64_t)(cnt - 1) * step;
     const int64_t nhi = lo + (int64_t)cnt * step;
     lo = nlo;
     hi = nhi < hi ? nhi : hi;
   }
-  while (lo + 1 < ntasks && uniform(cb[lo + 1]) <= item) lo++;
-  return lo;
 }
 
 }  // namespace tsds

@@ -161,8 +161,7 @@ __global__ __launch_bounds__(256) void k_batch_scan_nan(const BatchTask *__restr
   const int64_t i0 = total * w / W, i1 = total * (w + 1) / W;
 #pragma nounroll
   for (int64_t item = i0; item < i1; item++) {
-    const int64_t k = uniform(group_pos_of_item(cb, ntasks, item, lane));
-    const BatchTask *tk = tasks + uniform(tix[k]);
+    const BatchTask *tk = tasks + group_task_of_item(cb, tix, ntasks, item, lane);
     const ScanParams sp = task_scan_params_uniform(ws, tk, 0);
     scan_chunk_nan<T>(sp, item - uniform(tk->chunk_begin), lane);
   }
