@@ -697,7 +697,8 @@ def main():
     legs = set(x for x in args.legs.split(",") if x)
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the path shards by series or by index range, see the design notes)", file=sys.stderr)
+              "(a multi-GPU run would shard the series, or one series by index range, over the GPUs)",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
