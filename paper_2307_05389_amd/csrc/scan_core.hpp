@@ -1157,19 +1157,24 @@ __device__ inline void bin_range(const MergeParams &p, int64_t bin, int64_t &s, 
 // Sorted distinct selection of bin [s, e): MinMax keeps {argmin, argmax},
 // M4 adds the first and last index.  Writes up to 4 indices, returns the count.
 __device__ inline int bin_selection(int64_t s, int64_t e, int64_t imn, int64_t imx, int m4, int64_t *dst) {
-  int64_t v[4];
-  int k = 0;
-  if (m4) v[k++] = s;
-  v[k++] = imn;
-  v[k++] = imx;
-  if (m4) v[k++] = e - 1;
-  for (int a = 1; a < k; a++)
-    for (int c = a; c > 0 && v[c - 1] > v[c]; c--) {
-      int64_t t = v[c]; v[c] = v[c - 1]; v[c - 1] = t;
-    }
+  // the four candidates (MinMax: the argmin and argmax twice), sorted by a
+  // five-comparator network in registers, then written without repeats
+  int64_t v0 = m4 ? s : imn, v1 = imn, v2 = imx, v3 = m4 ? e - 1 : imx;
+  const auto cswap = [](int64_t &a, int64_t &b) {
+    const int64_t lo = a < b ? a : b, hi = a < b ? b : a;
+    a = lo;
+    b = hi;
+  };
+  cswap(v0, v1);
+  cswap(v2, v3);
+  cswap(v0, v2);
+  cswap(v1, v3);
+  cswap(v1, v2);
   int m = 0;
-  for (int a = 0; a < k; a++)
-    if (a == 0 || v[a] != v[a - 1]) dst[m++] = v[a];
+  dst[m++] = v0;
+  if (v1 != v0) dst[m++] = v1;
+  if (v2 != v1) dst[m++] = v2;
+  if (v3 != v2) dst[m++] = v3;
   return m;
 }
 
