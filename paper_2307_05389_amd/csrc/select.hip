@@ -215,6 +215,36 @@ __global__ __launch_bounds__(256) void k_compact_write(CompactParams p) {
   (void)compact_bins(p.cnt, p.sel, lo, hi, p.out, p.bsum[blockIdx.x], p.index_offset, lds);
 }
 
+// Up to kCompactPrefixBlocks workgroups: the offsets scan is folded into the
+// writes (two launches instead of three).  Every workgroup sums the block
+// sums in front of it itself (at most that many values, from L2) instead of
+// reading them from a separate scan; the last one also writes the count and
+// the end points.
+constexpr int64_t kCompactPrefixBlocks = 512;
+
+__global__ __launch_bounds__(256) void k_compact_write_prefix(CompactParams p, int64_t nblk) {
+  __shared__ int64_t lds[80];
+  const int64_t blk = blockIdx.x;
+  int64_t part = 0;
+  for (int64_t j = threadIdx.x; j < blk; j += blockDim.x) part += p.bsum[j];
+  int64_t before;
+  (void)block_exclusive_scan(part, lds, before);  // `before` = the block's total: sum of bsum[0, blk)
+  __syncthreads();
+  const int64_t lo = blk * kCompactBins;
+  const int64_t hi = lo + kCompactBins < p.nb ? lo + kCompactBins : p.nb;
+  (void)compact_bins(p.cnt, p.sel, lo, hi, p.out, before, p.index_offset, lds);
+  if (blk == nblk - 1 && threadIdx.x == 0) {
+    const int64_t total = before + p.bsum[blk];
+    if (p.endpoints_n > 0) {
+      p.out[-1] = 0;
+      p.out[total] = p.endpoints_n - 1;
+      *p.out_count = total + 2;
+    } else {
+      *p.out_count = total;
+    }
+  }
+}
+
 hipError_t launch_compact(const CompactParams &p, hipStream_t st) {
   if (p.all_n >= 0) {
     int64_t blocks = (p.all_n + 1023) / 1024;
@@ -229,6 +259,10 @@ hipError_t launch_compact(const CompactParams &p, hipStream_t st) {
   }
   const int64_t nblk = compact_blocks(p.nb);
   k_compact_sums<<<dim3((unsigned)nblk), dim3(256), 0, st>>>(p);
+  if (nblk <= kCompactPrefixBlocks) {
+    k_compact_write_prefix<<<dim3((unsigned)nblk), dim3(256), 0, st>>>(p, nblk);
+    return hipGetLastError();
+  }
   k_compact_offsets<<<dim3(1), dim3(1024), 0, st>>>(p, nblk);
   k_compact_write<<<dim3((unsigned)nblk), dim3(256), 0, st>>>(p);
   return hipGetLastError();

@@ -293,8 +293,16 @@ def test_staged_lanes_per_bin(ts, oracle_mod, dtype):
 @pytest.mark.parametrize("dtype", [np.float32, np.uint8, np.int64, np.float16])
 def test_many_bins_compaction(ts, oracle_mod, dtype):
     """Above 4,096 bins the compaction runs over many workgroups (block sums,
-    their scan, then the writes), 1,024 bins per workgroup; n <= n_out fills
-    0..n-1 from many workgroups.  Bin counts around both limits."""
+    then the writes, each workgroup summing the block sums in front of it; the
+    scan of the block sums in a launch of its own above 512 workgroups),
+    1,024 bins per workgroup; n <= n_out fills 0..n-1 from many workgroups.
+    Bin counts around the limits."""
+    if dtype == np.float32:
+        n2 = 1_200_007
+        y2 = S.walk(n2, dtype, seed=53)
+        for algo, n_out in (("minmax", 1_100_000), ("minmax", 2 * 512 * 1024), ("minmax", 2 * (512 * 1024 + 1))):
+            say(f"[many bins] {np.dtype(dtype).name} {algo} {n_out} (n={n2})")
+            assert np.array_equal(gpu(ts, algo, y2, n_out), orc(oracle_mod, algo, y2, n_out))
     n = 1_000_003
     y = S.walk(n, dtype, seed=51)
     x = S.timestamps(n, 40, seed=52)
