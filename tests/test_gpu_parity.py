@@ -94,11 +94,10 @@ def test_edge_sizes(ts, oracle_mod, algo):
                 assert np.array_equal(got, exp), (algo, dtype, n, n_out, got, exp)
 
 
-def test_ties_signed_zero_and_extremes(ts, oracle_mod):
+def _tie_cases(n):
     rng = np.random.default_rng(1)
-    n = 200003
     base = rng.integers(0, 3, n)
-    cases = {
+    return {
         "f64_zeros": np.where(base == 0, -0.0, np.where(base == 1, 0.0, 1.0)),
         "f32_inf": np.where(base == 0, -np.inf, np.where(base == 1, 0.0, np.inf)).astype(np.float32),
         "f16_zeros": np.where(base == 0, -0.0, np.where(base == 1, 0.0, -1.0)).astype(np.float16),
@@ -107,6 +106,10 @@ def test_ties_signed_zero_and_extremes(ts, oracle_mod):
         "i8_ext": np.where(base == 0, -128, np.where(base == 1, 0, 127)).astype(np.int8),
         "const": np.full(n, 7, np.int16),
     }
+
+
+def test_ties_signed_zero_and_extremes(ts, oracle_mod):
+    cases = _tie_cases(200003)
     for name, y in cases.items():
         for algo in ("minmax", "m4"):
             for n_out in (2 if algo == "minmax" else 4, 40, 4000, 100000):
@@ -267,6 +270,24 @@ def test_x_classified_chunks(ts, oracle_mod, xclass):
                         say(f"[xclass={xclass}] n={n} {np.dtype(dtype).name} x={name} minmaxlttb")
                         got = gpu(ts, "minmaxlttb", y, 200, xs[name], 4)
                         assert np.array_equal(got, orc(oracle_mod, "minmaxlttb", y, 200, xs[name], 4)), (n, name)
+    finally:
+        ts.set_tuning()
+
+
+def test_staged_vectors_ties(ts, oracle_mod):
+    """LDS-staged chunks with whole vectors per lane (bins of at least a
+    vector per lane): signed zeros, infinities and integer extremes repeat
+    across the lanes of a group and across vectors, so the first occurrence
+    rests on the (value, vector) reduction and the in-vector search."""
+    cases = _tie_cases(100003)
+    ts.set_tuning(-1, -1, -1, 1, -1)
+    try:
+        for name, y in cases.items():
+            for avg in (70, 300, 2000):
+                for algo, per in (("minmax", 2), ("m4", 4)):
+                    n_out = per * (len(y) // avg)
+                    say(f"[staged ties] {name} avg={avg} {algo} n_out={n_out}")
+                    assert np.array_equal(gpu(ts, algo, y, n_out), orc(oracle_mod, algo, y, n_out)), (name, avg)
     finally:
         ts.set_tuning()
 
