@@ -1097,6 +1097,36 @@ __device__ void scan_chunk_staged(const ScanParams &p, int64_t c, int lane, u32x
       const int k = __builtin_ctzll(big);
       big &= big - 1;
       const int64_t slo = readlane(lo, k), shi = readlane(hi, k);
+      if constexpr (VEC >= 4) {
+        // whole vectors across the wavefront: the per-vector fold, then the
+        // first vector holding each extreme and the first element in it
+        const uint32_t r0 = (uint32_t)(slo - g_base), r1 = (uint32_t)(shi - g_base);
+        const int32_t k1 = (int32_t)((r1 + VEC - 1) / VEC);
+        C vmn = E::highest(), vmx = E::lowest();
+        int32_t kmn = INT32_MAX, kmx = INT32_MAX;
+        for (int32_t kv = (int32_t)(r0 / VEC) + lane; kv < k1; kv += kWave) {
+          const u32x4 d = lds[kv];
+          const uint32_t q0 = (uint32_t)kv * VEC;
+          C a, x;
+          if (q0 >= r0 && q0 + VEC <= r1) {
+            VecOps<T>::minmax(d, a, x);
+          } else {
+            vec_minmax_masked<T>(d, q0, r0, r1, a, x);
+          }
+          if (kmn == INT32_MAX || a < vmn) { vmn = a; kmn = kv; }
+          if (kmx == INT32_MAX || vmx < x) { vmx = x; kmx = kv; }
+        }
+        const C wmn = wave_min(vmn), wmx = wave_max(vmx);
+        const int32_t vn = (int32_t)uniform(wave_min((int64_t)(kmn != INT32_MAX && vmn == wmn ? kmn : INT32_MAX)));
+        const int32_t vx = (int32_t)uniform(wave_min((int64_t)(kmx != INT32_MAX && vmx == wmx ? kmx : INT32_MAX)));
+        const int jn = vec_first_masked<T>(lds[vn], wmn, (uint32_t)vn * VEC, r0, r1);
+        const int jx = vec_first_masked<T>(lds[vx], wmx, (uint32_t)vx * VEC, r0, r1);
+        const bool sb = readlane(s, k) < c0, sa = readlane(e, k) > c1;
+        if (lane == 0)
+          write_result<T>(p, c, b + k, sb, sa, wmn, g_base + (int64_t)vn * VEC + jn, wmx,
+                          g_base + (int64_t)vx * VEC + jx);
+        continue;
+      }
       // per lane: elements slo + lane + 64 i in index order, strict compares,
       // four LDS reads in flight per step
       C vmn = E::highest(), vmx = E::lowest();
