@@ -191,3 +191,22 @@ def test_nan_batched(ts, oracle_mod):
                 assert np.array_equal(res[i], one), (chunk, graph, i)
     finally:
         b.close()
+
+
+@pytest.mark.parametrize("dt", FLOATS)
+def test_nan_signed_zero_and_inf(ts, oracle_mod, dt):
+    """Signed zeros, infinities and NaN repeated across lanes and vectors:
+    the first occurrence of an extreme (zeros compare equal) must match the
+    oracle, also where a vector holds only NaN or only infinities."""
+    rng = np.random.default_rng(7)
+    n = 200003
+    pick = rng.integers(0, 6, n)
+    y = np.choose(pick, [np.float64(-0.0), 0.0, -np.inf, np.inf, np.nan, 1.0]).astype(dt)
+    y[1000:5000] = np.nan
+    y[9000:9100] = np.inf
+    for kind, per in (("minmax", 2), ("m4", 4)):
+        for nb in (3, 40, 1000, 20000):
+            say(f"[nan zeros/inf] {np.dtype(dt).name} {kind} nb={nb}")
+            got = run(ts, kind, y, per * nb, None)
+            exp = getattr(oracle_mod, "nan_" + kind)(y, per * nb)
+            assert np.array_equal(got, exp), (kind, nb)
