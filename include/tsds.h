@@ -136,7 +136,8 @@ int ts_minmaxlttb(const ts_series *s, int64_t n_out, int64_t minmax_ratio, int64
  * ts_minmaxlttb on the stream's device (NULL stream: the current device).
  * Errors: TS_ERR_WORKSPACE, before anything touches the GPU, when
  * ts_workspace_bytes(TS_MINMAXLTTB, s, n_out, minmax_ratio) exceeds the
- * scratch (about 4 GB of y); otherwise ts_minmaxlttb's checks and codes.
+ * scratch (n_out of a few thousand: up to ~16 GB of y; n_out ~200,000: a
+ * few GB); otherwise ts_minmaxlttb's checks and codes.
  * The scratch needs no initial content, and every call on a GPU reuses that
  * GPU's one array: calls whose work overlaps in time on the same GPU (two
  * streams, two host threads) race on it and must be serialised by the

@@ -17,8 +17,10 @@
 
 namespace tsds {
 
-// 64 MiB: MinMaxLTTB needs about 16 bytes of workspace per KB of y (per-chunk
-// partials), so series up to ~4 GB of y (1e9 float32 points) fit.
+// 64 MiB: MinMaxLTTB's workspace is about 4 bytes per KB of y (per-chunk
+// partials) plus about 260 bytes per output point (bins, candidates, the LTTB
+// map), so n_out of a few thousand fits series up to ~16 GB of y, and n_out
+// up to ~200,000 fits series of a few GB.
 constexpr size_t kScratchBytes = (size_t)64 << 20;
 
 static __device__ __align__(256) unsigned char scratch[kScratchBytes];
