@@ -358,9 +358,11 @@ void ts_server_free(ts_server *server);
  * xclass (-1 = automatic: on for int64 x when bins average at least two
  * chunks, 0 = off, 1 = on; int64 x and unstaged scans only) lets each chunk
  * find its bins from x directly, so that the edge array is written by the scan
- * instead of a separate edge search; direct (-1 = automatic: small series,
- * and series without x whose bins are 2-64 KB, at least 2048 of them; 0 =
- * off, 1 = on for every MinMax / M4 call and preselection) gives each bin one
+ * instead of a separate edge search; direct (-1 = automatic: series up to
+ * 8 MB in at least 64 bins of at least 256 elements, and series without x
+ * in at least 2,000 bins of 4-512 KB, or f64 in at least 1,000 bins of at
+ * least 256 KB; 0 = off, 1 = on for every MinMax / M4 call and
+ * preselection) gives each bin one
  * wavefront that reduces the whole bin and writes its selection (no chunks,
  * partials or merge; any other override set switches the automatic choice
  * off).
