@@ -360,12 +360,14 @@ void ts_server_free(ts_server *server);
  * find its bins from x directly, so that the edge array is written by the scan
  * instead of a separate edge search; direct (-1 = automatic: series up to
  * 8 MB in at least 64 bins of at least 256 elements, and series without x
- * in at least 2,000 bins of 4-512 KB, or f64 in at least 1,000 bins of at
- * least 256 KB; 0 = off, 1 = on for every MinMax / M4 call and
- * preselection) gives each bin one
- * wavefront that reduces the whole bin and writes its selection (no chunks,
- * partials or merge; any other override set switches the automatic choice
- * off).
+ * in at least 2,000 bins of 4-512 KB, get a wavefront per bin; series
+ * without x in 500-1,999 bins (eight-byte types 250-1,999) of at least
+ * 256 KB get a workgroup per bin;
+ * 0 = off, 1 = a wavefront per bin, 2 = a workgroup of four wavefronts per
+ * bin, for every MinMax / M4 call and preselection) gives each bin one
+ * wavefront or workgroup that reduces the whole bin and writes its
+ * selection (no chunks, partials or merge; any other override set switches
+ * the automatic choice off).
  * Results never depend on them; workspace sizes do, so query
  * ts_workspace_bytes after a change.  Not thread-safe with concurrent
  * compute calls. */
@@ -375,7 +377,8 @@ int ts_set_tuning(int64_t chunk_bytes, int32_t small_bin, int32_t scan_variant, 
 /* Host-side query: the scan's tile variant, chunk size (bytes) and kind
  * (0 = chunks with an edge array or closed-form bins, 1 = LDS-staged,
  * 2 = classified from int64 x, 3 = chunks streamed tile by tile over their
- * bins, 4 = one wavefront per bin, no chunks) for n elements of y_dtype in nb
+ * bins, 4 = one wavefront per bin, no chunks, 5 = one workgroup of four
+ * wavefronts per bin, no chunks) for n elements of y_dtype in nb
  * bins, x of x_dtype (TS_NONE: no x), under the current tuning. */
 int ts_scan_config(int y_dtype, int x_dtype, int64_t n, int64_t nb, int32_t *variant, int64_t *chunk_bytes,
                    int32_t *kind);

@@ -107,9 +107,10 @@ def scan_config(dtype, n, nb=1, x_dtype=None):
     check(lib().ts_scan_config(DTYPE_CODES[dtype], xd, int(n), int(nb), ctypes.byref(v), ctypes.byref(c),
                                ctypes.byref(k)))
     ct = CTYPE_NAME[DTYPE_CODES[dtype]]
-    if k.value == 4:
+    if k.value in (4, 5):
         u, nbuf = VARIANT_SHAPE[v.value]
-        return v.value, c.value, f"tsds::k_bins_direct<{ct}, {u}, {nbuf}>"
+        name = "k_bins_direct" if k.value == 4 else "k_bins_block"
+        return v.value, c.value, f"tsds::{name}<{ct}, {u}, {nbuf}>"
     if k.value == 1:
         return v.value, c.value, f"tsds::k_scan_staged<{ct}>"
     if k.value == 3:

@@ -89,18 +89,21 @@ static int32_t g_direct_override = -1;
 // kDirectMinBins bins of at least kDirectMinBin elements (the call is
 // launch-bound there), and series without x (equal bins, so every wavefront
 // reads the same amount) in at least kDirectWideMinBins bins of
-// kDirectWideMinBinBytes..kDirectWideMaxBinBytes (eight-byte types from
-// kDirectWideMinBins8 bins of at least kDirectWide8MinBinBytes).  Sweeps of
-// MinMax over 1 GB series on MI355X (u8, i16, f16, f32, f64; bins of 5 KB to
-// 1 MB): from 5 KB to 500 KB bins the per-bin wavefront is the fastest path
-// for every type (10 KB u8 bins 3.8 -> 5.7 TB/s, 10 KB f32 bins 4.8 -> 6.0
-// TB/s, 500 KB bins 5.7-6.1 -> 6.2-6.6 TB/s); below ~4 KB the LDS-staged
-// chunks win, and with 1,000 bins there are too few wavefronts and the
-// chunked scan wins (u8 3.9 against 6.0 TB/s), except for f64, whose fold is
-// the cheapest per byte (6.5 against 6.1 TB/s).
+// kDirectWideMinBinBytes..kDirectWideMaxBinBytes.  From kBlockMinBins to
+// kDirectWideMinBins bins of at least kBlockMinBinBytes, a wavefront each
+// leaves the GPU half empty: a workgroup of four wavefronts per bin instead.
+// Sweeps of MinMax over 1 GB series on MI355X (u8, i16, f16, f32, f64; bins
+// of 3 KB to 4 MB): from 4 KB to 500 KB bins the per-bin wavefront is the
+// fastest path for every type (10 KB u8 bins 3.8 -> 5.8 TB/s, 10 KB f32 bins
+// 4.8 -> 6.1 TB/s, 500 KB bins 6.1 -> 6.3-6.6 TB/s); below ~4 KB the
+// LDS-staged chunks win; with 500-1,999 bins the workgroup per bin (1,000
+// bins: u8 3.9 TB/s with a wavefront per bin, 6.1 with chunks, 6.2 with a
+// workgroup per bin; f32 4.4 / 6.1 / 6.4; 500 bins: f32 2.4 / 6.1 / 6.6,
+// f64 3.9 / 6.0 / 6.6); with 250 bins (4 MB) the chunks win again except
+// for f64 (6.2 with chunks, 6.6 with a workgroup per bin).
 static const int64_t kDirectMaxBytes = 8 << 20, kDirectMinBins = 64, kDirectMinBin = 256;
 static const int64_t kDirectWideMinBins = 2000, kDirectWideMinBinBytes = 4096, kDirectWideMaxBinBytes = 512 << 10;
-static const int64_t kDirectWideMinBins8 = 1000, kDirectWide8MinBinBytes = 256 << 10;
+static const int64_t kBlockMinBins = 500, kBlockMinBins8 = 250, kBlockMinBinBytes = 256 << 10;
 
 // The per-bin grid has 64 threads per bin: at most 2^25 bins keeps it within
 // 2^31 threads.
@@ -120,18 +123,25 @@ static int32_t direct_variant(int ydt, int64_t bin_bytes) {
   return es == 8 && bin_bytes >= 32768 ? 2 : 0;
 }
 
-static bool direct_bins(int ydt, bool has_x, int64_t n, int64_t nb) {
-  if (nb > kDirectMaxBinCount) return false;
-  if (g_direct_override >= 0) return g_direct_override == 1;
+// 0: chunks (partials, merge); 1: a wavefront per bin; 2: a workgroup of four
+// wavefronts per bin (long bins, too few for a wavefront each).
+static int direct_mode(int ydt, bool has_x, int64_t n, int64_t nb) {
+  if (nb > kDirectMaxBinCount) return 0;
+  if (g_direct_override >= 0) return g_direct_override;
   if (g_chunk_bytes_override >= 0 || g_small_override >= 0 || g_variant_override >= 0 || g_stage_override >= 0)
-    return false;  // explicit chunk tuning: the chunked kernels run
+    return 0;  // explicit chunk tuning: the chunked kernels run
   const int64_t es = (int64_t)elem_size(ydt);
-  if (n * es <= kDirectMaxBytes && nb >= kDirectMinBins && n / nb >= kDirectMinBin) return true;
+  if (n * es <= kDirectMaxBytes && nb >= kDirectMinBins && n / nb >= kDirectMinBin) return 1;
   const int64_t bin_bytes = n / nb * es;
-  if (has_x || bin_bytes < kDirectWideMinBinBytes) return false;
-  if (es == 8 && nb >= kDirectWideMinBins8 && bin_bytes >= kDirectWide8MinBinBytes) return true;
-  return nb >= kDirectWideMinBins && bin_bytes <= kDirectWideMaxBinBytes;
+  if (has_x || bin_bytes < kDirectWideMinBinBytes) return 0;
+  if (nb >= (es == 8 ? kBlockMinBins8 : kBlockMinBins) && nb < kDirectWideMinBins && bin_bytes >= kBlockMinBinBytes)
+    return 2;
+  return nb >= kDirectWideMinBins && bin_bytes <= kDirectWideMaxBinBytes ? 1 : 0;
 }
+
+// Tile shape of the workgroup-per-bin kernel: 8x1 for eight-byte types, else
+// 4x1 (sweeps over 1 GB series, 500-1,500 bins).
+static int32_t block_variant(int ydt) { return elem_size(ydt) == 8 ? 2 : 1; }
 
 // Bins averaging fewer than kStageBin elements go through LDS-staged chunks
 // of kStageChunk bytes (one HBM round trip per chunk instead of one per bin).
@@ -425,7 +435,8 @@ static int run_scan(const ts_series &s, int64_t nb, int m4, const ScanPlan &pl, 
   sp.xedges = pl.xclass ? ed : nullptr;
   if (pl.xclass) sp.edges = nullptr;
   // one wavefront per bin, no merge (not while the scan kernel is being timed)
-  const bool direct = !pl.nan && !pl.xclass && !g_ev_start && direct_bins(s.y_dtype, s.x != nullptr, s.n, nb);
+  const int dmode = !pl.nan && !pl.xclass && !g_ev_start ? direct_mode(s.y_dtype, s.x != nullptr, s.n, nb) : 0;
+  const bool direct = dmode > 0;
   if (pl.nan) {
     if ((e = launch_scan_nan(s.y_dtype, sp, st)) != hipSuccess) return hip_fail(e, "nan scan");
   } else if (!direct && (e = launch_scan(s.y_dtype, sp, st, g_ev_start, g_ev_stop)) != hipSuccess) {
@@ -455,10 +466,11 @@ static int run_scan(const ts_series &s, int64_t nb, int m4, const ScanPlan &pl, 
   cp.bsum = nb > kCompactSingleMax ? (int64_t *)wsp(ws, pl.off_bsum) : nullptr;
   if (direct) {
     ScanParams dp = sp;
-    dp.variant = g_variant_override >= 0 && g_variant_override < kScanStreamVariant
-                     ? g_variant_override
-                     : direct_variant(s.y_dtype, s.n / nb * (int64_t)elem_size(s.y_dtype));
-    if ((e = launch_bins_direct(s.y_dtype, dp, mp, st)) != hipSuccess) return hip_fail(e, "bins");
+    dp.variant = g_variant_override >= 0 && g_variant_override < kScanStreamVariant ? g_variant_override
+                 : dmode == 2 ? block_variant(s.y_dtype)
+                              : direct_variant(s.y_dtype, s.n / nb * (int64_t)elem_size(s.y_dtype));
+    e = dmode == 2 ? launch_bins_block(s.y_dtype, dp, mp, st) : launch_bins_direct(s.y_dtype, dp, mp, st);
+    if (e != hipSuccess) return hip_fail(e, "bins");
   } else if ((e = launch_merge(mp, st)) != hipSuccess) {
     return hip_fail(e, "merge");
   }
@@ -840,7 +852,7 @@ int ts_set_tuning(int64_t chunk_bytes, int32_t small_bin, int32_t scan_variant, 
   if (scan_variant > kScanStreamVariant) return fail(TS_ERR_ARG, "scan_variant must be -1..4");
   if (stage > 1) return fail(TS_ERR_ARG, "stage must be -1, 0 or 1");
   if (xclass > 1) return fail(TS_ERR_ARG, "xclass must be -1, 0 or 1");
-  if (direct > 1) return fail(TS_ERR_ARG, "direct must be -1, 0 or 1");
+  if (direct > 2) return fail(TS_ERR_ARG, "direct must be -1, 0, 1 or 2");
   g_direct_override = direct < 0 ? -1 : direct;
   g_chunk_bytes_override = chunk_bytes;
   g_small_override = small_bin;
@@ -860,11 +872,12 @@ int ts_scan_config(int y_dtype, int x_dtype, int64_t n, int64_t nb, int32_t *var
   *variant = sh.variant;
   *chunk_bytes = sh.chunk_bytes;
   *kind = sh.stage ? 1 : sh.xclass ? 2 : sh.variant == kScanStreamVariant ? 3 : 0;
-  if (!sh.xclass && direct_bins(y_dtype, x_dtype != TS_NONE, n, nb)) {
-    *kind = 4;
-    *variant = g_variant_override >= 0 && g_variant_override < kScanStreamVariant
-                   ? g_variant_override
-                   : direct_variant(y_dtype, n / nb * (int64_t)elem_size(y_dtype));
+  const int dmode = sh.xclass ? 0 : direct_mode(y_dtype, x_dtype != TS_NONE, n, nb);
+  if (dmode) {
+    *kind = dmode == 2 ? 5 : 4;
+    *variant = g_variant_override >= 0 && g_variant_override < kScanStreamVariant ? g_variant_override
+               : dmode == 2 ? block_variant(y_dtype)
+                            : direct_variant(y_dtype, n / nb * (int64_t)elem_size(y_dtype));
   }
   return TS_OK;
 }

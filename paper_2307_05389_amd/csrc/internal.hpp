@@ -86,6 +86,7 @@ hipError_t launch_merge(const MergeParams &p, hipStream_t st);
 // Small series: one wavefront per bin, selection written directly (replaces
 // the scan and the merge).
 hipError_t launch_bins_direct(int y_dtype, const ScanParams &sp, const MergeParams &mp, hipStream_t st);
+hipError_t launch_bins_block(int y_dtype, const ScanParams &sp, const MergeParams &mp, hipStream_t st);
 hipError_t launch_compact(const CompactParams &p, hipStream_t st);
 hipError_t launch_binres_to_outputs(const MergeParams &p, int64_t *imin, int64_t *imax,
                                     hipStream_t st);

@@ -87,6 +87,97 @@ static void launch_direct_t(int variant, dim3 grid, dim3 block, const ScanParams
 }
 
 // sp.variant picks the tile shape (0 = 4x2, 1 = 4x1, 2 = 8x1, 3 = 2x2).
+// Long bins and too few of them for a wavefront each to fill the GPU: a
+// workgroup of kBlockWaves wavefronts per bin, wavefront w reducing the w-th
+// contiguous part of the bin (the same tile fold), then the first wavefront's
+// first lane combining the parts in index order (strict comparisons: an
+// equal extreme in a later part never replaces an earlier one) and writing
+// the bin's selection.
+constexpr int kBlockWaves = 4;
+
+template <typename T, int U, int NB>
+__global__ __launch_bounds__(64 * kBlockWaves) void k_bins_block(ScanParams sp, MergeParams mp) {
+  using C = typename Elem<T>::C;
+  __shared__ C smn[kBlockWaves], smx[kBlockWaves];
+  __shared__ int64_t simn[kBlockWaves], simx[kBlockWaves];
+  __shared__ int shas[kBlockWaves];
+  const int64_t bin = uniform((int64_t)blockIdx.x);
+  const int w = uniform((int)(threadIdx.x >> 6));
+  const int lane = lane_id();
+  int64_t s, e;
+  bin_range(mp, bin, s, e);
+  if (s >= e) {  // the same for the whole workgroup
+    if (threadIdx.x == 0) mp.cnt[bin] = 0;
+    return;
+  }
+  const int64_t len = e - s;
+  const int64_t w0 = uniform(s + len * w / kBlockWaves), w1 = uniform(s + len * (w + 1) / kBlockWaves);
+  SegState<C> st;
+  st.has = false;
+  if (w0 < w1) {
+    const u32x4 *__restrict__ base = (const u32x4 *)((const T *)sp.y - sp.shift);
+    u32x4 buf[NB][U];
+    wave_segment<T, U, NB>(base, sp.shift, w0, w1, lane, buf, 0, st);
+  }
+  if (lane == 0) {
+    smn[w] = st.vmn;
+    smx[w] = st.vmx;
+    simn[w] = st.imn;
+    simx[w] = st.imx;
+    shas[w] = st.has ? 1 : 0;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    C vmn = smn[0], vmx = smx[0];
+    int64_t imn = simn[0], imx = simx[0];
+    bool has = false;
+    for (int k = 0; k < kBlockWaves; k++) {
+      if (!shas[k]) continue;
+      if (!has || smn[k] < vmn) {
+        vmn = smn[k];
+        imn = simn[k];
+      }
+      if (!has || vmx < smx[k]) {
+        vmx = smx[k];
+        imx = simx[k];
+      }
+      has = true;
+    }
+    mp.cnt[bin] = bin_selection(s, e, imn, imx, mp.m4, mp.sel + 4 * bin);
+  }
+}
+
+template <typename T>
+static void launch_block_t(int variant, dim3 grid, dim3 block, const ScanParams &sp, const MergeParams &mp,
+                           hipStream_t st) {
+  switch (variant) {
+    case 1: k_bins_block<T, 4, 1><<<grid, block, 0, st>>>(sp, mp); break;
+    case 2: k_bins_block<T, 8, 1><<<grid, block, 0, st>>>(sp, mp); break;
+    case 3: k_bins_block<T, 2, 2><<<grid, block, 0, st>>>(sp, mp); break;
+    default: k_bins_block<T, 4, 2><<<grid, block, 0, st>>>(sp, mp); break;
+  }
+}
+
+hipError_t launch_bins_block(int ydt, const ScanParams &sp, const MergeParams &mp, hipStream_t st) {
+  const dim3 grid((unsigned)mp.nb), block(64 * kBlockWaves);
+  const int v = sp.variant;
+  switch (ydt) {
+    case TS_I8: launch_block_t<int8_t>(v, grid, block, sp, mp, st); break;
+    case TS_I16: launch_block_t<int16_t>(v, grid, block, sp, mp, st); break;
+    case TS_I32: launch_block_t<int32_t>(v, grid, block, sp, mp, st); break;
+    case TS_I64: launch_block_t<int64_t>(v, grid, block, sp, mp, st); break;
+    case TS_U8: launch_block_t<uint8_t>(v, grid, block, sp, mp, st); break;
+    case TS_U16: launch_block_t<uint16_t>(v, grid, block, sp, mp, st); break;
+    case TS_U32: launch_block_t<uint32_t>(v, grid, block, sp, mp, st); break;
+    case TS_U64: launch_block_t<uint64_t>(v, grid, block, sp, mp, st); break;
+    case TS_F16: launch_block_t<half_t>(v, grid, block, sp, mp, st); break;
+    case TS_F32: launch_block_t<float>(v, grid, block, sp, mp, st); break;
+    case TS_F64: launch_block_t<double>(v, grid, block, sp, mp, st); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_bins_direct(int ydt, const ScanParams &sp, const MergeParams &mp, hipStream_t st) {
   const dim3 grid((unsigned)((mp.nb + 3) / 4)), block(256);
   const int v = sp.variant;

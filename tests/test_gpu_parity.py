@@ -193,23 +193,26 @@ def _direct_cases(ts, oracle_mod, y, x, off, tag):
 @pytest.mark.parametrize("dtype", [np.uint8, np.int8, np.int16, np.float16, np.float32, np.int32, np.float64,
                                    np.uint64])
 def test_direct_bins(ts, oracle_mod, dtype):
-    """One wavefront per bin reducing the whole bin (no chunks, no merge):
-    forced on for bins of one element to the whole series, with and without
-    x, off the 16-byte grid; and chosen automatically for series without x
-    above the small-series limit whose bins are a few kilobytes."""
+    """One wavefront, or one workgroup of four, per bin reducing the whole bin
+    (no chunks, no merge): forced on for bins of one element to the whole
+    series, with and without x, off the 16-byte grid; and chosen
+    automatically for series without x above the small-series limit (a
+    wavefront for >= 2000 bins of a few kilobytes, a workgroup for 500-1999
+    bins, 250-1999 for eight-byte types, of >= 256 KB)."""
     n = 300_007
     y = S.walk(n, dtype, seed=81)
     S.tie_runs(y, 0.1, seed=82)
     x = S.timestamps(n, 40, seed=83)
     try:
-        for variant in (-1, 0, 1, 2, 3):     # the automatic tile shape, then each shape
-            ts.set_tuning(direct=1, scan_variant=variant)
-            for off in ((0, 5) if variant == -1 else (5,)):
-                _direct_cases(ts, oracle_mod, y, x, off, f"{np.dtype(dtype).name} variant={variant}")
+        for mode in (1, 2):                  # a wavefront per bin, a workgroup per bin
+            for variant in (-1, 0, 1, 2, 3):     # the automatic tile shape, then each shape
+                ts.set_tuning(direct=mode, scan_variant=variant)
+                for off in ((0, 5) if variant == -1 else (5,)):
+                    _direct_cases(ts, oracle_mod, y, x, off, f"{np.dtype(dtype).name} mode={mode} variant={variant}")
     finally:
         ts.set_tuning()
-    # automatic choice: > 8 MB, no x, >= 2000 bins of 4-512 KB (eight-byte
-    # types also 1000 bins of >= 256 KB)
+    # automatic choice: > 8 MB, no x, >= 2000 bins of 4-512 KB; 500-1999 bins
+    # (eight-byte types 250-1999) of >= 256 KB: a workgroup per bin
     from paper_2307_05389_amd import _lib as L
     es = np.dtype(dtype).itemsize
     nbig = (16 << 20) // es + 13
@@ -222,14 +225,22 @@ def test_direct_bins(ts, oracle_mod, dtype):
         for algo, per in (("minmax", 2), ("m4", 4)):
             say(f"[direct auto] {np.dtype(dtype).name} bin_bytes={bin_bytes} {algo}")
             assert np.array_equal(gpu(ts, algo, ybig, per * nb), orc(oracle_mod, algo, ybig, per * nb))
-    if es == 8:
-        n8 = 1000 * (1 << 15) + 7
+    if dtype in (np.uint8, np.float32, np.float64):
+        nbb = 503
+        n8 = nbb * (256 << 10) // es + 7
         y8 = S.walk(n8, dtype, seed=85)
-        assert L.scan_config(dev(y8[:8]).dtype, n8, 1000)[2].startswith("tsds::k_bins_direct<")
-        assert not L.scan_config(dev(y8[:8]).dtype, n8 // 2, 1000)[2].startswith("tsds::k_bins_direct<")
+        S.tie_runs(y8, 0.05, seed=86)
+        td = dev(y8[:8]).dtype
+        assert L.scan_config(td, n8, nbb)[2].startswith("tsds::k_bins_block<")
+        assert L.scan_config(td, n8, 4 * nbb)[2].startswith("tsds::k_bins_direct<")  # 64 KB bins: a wave each
+        assert not L.scan_config(td, n8 // 2, nbb)[2].startswith("tsds::k_bins")  # 128 KB bins: chunks
+        assert L.scan_config(td, n8, 499)[2].startswith("tsds::k_bins_block<") == (es == 8)
+        assert not L.scan_config(td, n8, 249)[2].startswith("tsds::k_bins_block<")
         for algo, per in (("minmax", 2), ("m4", 4)):
-            say(f"[direct auto] {np.dtype(dtype).name} 1000 bins of 256 KB {algo}")
-            assert np.array_equal(gpu(ts, algo, y8, per * 1000), orc(oracle_mod, algo, y8, per * 1000))
+            say(f"[block auto] {np.dtype(dtype).name} {nbb} bins of 256 KB {algo}")
+            assert np.array_equal(gpu(ts, algo, y8, per * nbb), orc(oracle_mod, algo, y8, per * nbb))
+        say(f"[block auto] {np.dtype(dtype).name} minmaxlttb 2 * {nbb}")
+        assert np.array_equal(gpu(ts, "minmaxlttb", y8, 2 * nbb), orc(oracle_mod, "minmaxlttb", y8, 2 * nbb))
 
 
 def x_patterns(n, seed):
