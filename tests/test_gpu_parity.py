@@ -117,6 +117,23 @@ def test_ties_signed_zero_and_extremes(ts, oracle_mod):
                 assert np.array_equal(gpu(ts, algo, y, n_out), orc(oracle_mod, algo, y, n_out)), (name, algo, n_out)
 
 
+@pytest.mark.parametrize("mode", [1, 2])
+def test_ties_per_bin_modes(ts, oracle_mod, mode):
+    """The tie and extreme-value cases with a wavefront per bin (mode 1) and
+    a workgroup of four per bin (mode 2, where the wavefronts' results meet
+    in LDS): the first index of a tie and -0 / +0 order must survive both."""
+    cases = _tie_cases(200003)
+    try:
+        ts.set_tuning(direct=mode)
+        for name, y in cases.items():
+            for algo in ("minmax", "m4"):
+                for n_out in (2 if algo == "minmax" else 4, 40, 4000):
+                    say(f"[ties mode={mode}] {name} {algo} n_out={n_out}")
+                    assert np.array_equal(gpu(ts, algo, y, n_out), orc(oracle_mod, algo, y, n_out)), (name, algo, n_out)
+    finally:
+        ts.set_tuning()
+
+
 @pytest.mark.parametrize("chunk,small,stage,xclass",
                          [(4096, -1, 0, -1), (4096, 1, 0, -1), (65536, 100000, 0, -1), (8192, 7, 0, -1),
                           (-1, 1 << 20, 0, -1), (8192, -1, 1, -1), (4096, -1, 1, -1), (32768, -1, 1, -1),
