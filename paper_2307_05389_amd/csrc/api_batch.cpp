@@ -272,13 +272,13 @@ int tsds::batch_enqueue(const ts_plan *p, const void *d_table, int64_t *out, int
   // bytes weighted by how slowly its kernel moves them: staged groups (many
   // small bins, latency-bound) x4; chunked scans of bytes x3, of 16-bit
   // types x1.5 (measured on the 512-series mix: 0.687 -> 0.640 ms against
-  // bytes-only ordering); groups reduced a wavefront per bin x1, bytes x4
-  // (alone on the GPU the byte group moves ~1.7 TB/s where the others move
-  // ~5: its fold keeps four wavefronts per SIMD), so that it starts first.
+  // bytes-only ordering); groups reduced a wavefront per bin by their rates
+  // alone on the GPU: bytes x2, 16-bit types x1.15, else x1 (bytes ~2.8,
+  // 16-bit ~5.1, wider ~5.9 TB/s).
   auto cost = [p](int g) {
     const bool staged = g < 22 && g / 11 == 1, direct = g >= kBatchDirectGroup;
     const size_t es = esize(g % 11);
-    if (direct) return p->group_bytes[g] * (es == 1 ? 4.0 : 1.0);
+    if (direct) return p->group_bytes[g] * (es == 1 ? 2.0 : es == 2 ? 1.15 : 1.0);
     return p->group_bytes[g] * (staged ? 4.0 : es == 1 ? 3.0 : es == 2 ? 1.5 : 1.0);
   };
   std::vector<int> order;
@@ -316,6 +316,25 @@ int tsds::batch_enqueue(const ts_plan *p, const void *d_table, int64_t *out, int
       queue_of[k] = best;
       load[best] += cost(order[k]);
     }
+  }
+  // The per-bin byte group is enqueued first on whichever stream it shares:
+  // its many short dependent tile chains overlap best with everything else
+  // from the start.  512-series mix, two best tunings: these weights with the
+  // byte group first 0.551-0.555 ms; the same with it behind the f16 group
+  // 0.571-0.578 ms; bytes x4 and 16-bit x1 (the byte group alone on a stream,
+  // the two 16-bit groups one after the other) 0.557-0.560 ms.
+  {
+    std::vector<size_t> li(order.size());
+    for (size_t k = 0; k < li.size(); k++) li[k] = k;
+    std::stable_partition(li.begin(), li.end(),
+                          [&](size_t k) { return order[k] >= kBatchDirectGroup && esize(order[k] % 11) == 1; });
+    std::vector<int> o2(order.size()), q2(order.size());
+    for (size_t k = 0; k < li.size(); k++) {
+      o2[k] = order[li[k]];
+      q2[k] = queue_of[li[k]];
+    }
+    order.swap(o2);
+    queue_of.swap(q2);
   }
   for (size_t k = 0; k < order.size(); k++) {
     const int g = order[k];
