@@ -364,7 +364,8 @@ void ts_server_free(ts_server *server);
  * without x in 500-1,999 bins (eight-byte types 250-1,999) of at least
  * 256 KB get a workgroup per bin;
  * 0 = off, 1 = a wavefront per bin, 2 = a workgroup of four wavefronts per
- * bin, for every MinMax / M4 call and preselection) gives each bin one
+ * bin (a wavefront per bin above 2^23 bins), for every MinMax / M4 call and
+ * preselection; neither above 2^25 bins) gives each bin one
  * wavefront or workgroup that reduces the whole bin and writes its
  * selection (no chunks, partials or merge; any other override set switches
  * the automatic choice off).

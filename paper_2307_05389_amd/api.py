@@ -166,7 +166,8 @@ def set_tuning(chunk_bytes=-1, small_bin=-1, scan_variant=-1, stage=-1, xclass=-
     """Override the scan's chunk size (power of two >= 4096 bytes), the
     segment length below which one lane handles a whole bin, the tile shape
     variant, LDS staging, the classification of chunks from int64 x and the
-    one-wavefront-per-bin path; -1 restores the defaults.  Results do not
-    depend on them."""
+    per-bin paths (direct: 0 = chunks, 1 = a wavefront per bin, 2 = a
+    workgroup of four wavefronts per bin); -1 restores the defaults.  Results
+    do not depend on them."""
     L.check(L.lib().ts_set_tuning(int(chunk_bytes), int(small_bin), int(scan_variant), int(stage), int(xclass),
                                   int(direct)))

@@ -106,8 +106,8 @@ static const int64_t kDirectWideMinBins = 2000, kDirectWideMinBinBytes = 4096, k
 static const int64_t kBlockMinBins = 500, kBlockMinBins8 = 250, kBlockMinBinBytes = 256 << 10;
 
 // The per-bin grid has 64 threads per bin: at most 2^25 bins keeps it within
-// 2^31 threads.
-static const int64_t kDirectMaxBinCount = (int64_t)1 << 25;
+// 2^31 threads; the workgroup-per-bin grid has 256, so at most 2^23 bins.
+static const int64_t kDirectMaxBinCount = (int64_t)1 << 25, kBlockMaxBinCount = (int64_t)1 << 23;
 
 // Tile shape of the per-bin kernel (the scan's variant numbering: 0 = 4x2,
 // 1 = 4x1, 2 = 8x1, 3 = 2x2) from the same sweeps: bytes 4x1 (their fold
@@ -127,7 +127,7 @@ static int32_t direct_variant(int ydt, int64_t bin_bytes) {
 // wavefronts per bin (long bins, too few for a wavefront each).
 static int direct_mode(int ydt, bool has_x, int64_t n, int64_t nb) {
   if (nb > kDirectMaxBinCount) return 0;
-  if (g_direct_override >= 0) return g_direct_override;
+  if (g_direct_override >= 0) return g_direct_override == 2 && nb > kBlockMaxBinCount ? 1 : g_direct_override;
   if (g_chunk_bytes_override >= 0 || g_small_override >= 0 || g_variant_override >= 0 || g_stage_override >= 0)
     return 0;  // explicit chunk tuning: the chunked kernels run
   const int64_t es = (int64_t)elem_size(ydt);

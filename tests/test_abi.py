@@ -140,3 +140,29 @@ def test_downsampler_argument_parsing_before_any_device_work():
         t.M4Downsampler().downsample(y, n_out=8, minmax_ratio=2)  # MinMaxLTTB-only keyword
     with pytest.raises(TypeError):
         t.LTTBDownsampler().downsample(y, y, y, 4)               # too many arrays
+
+
+def test_per_bin_mode_host_logic():
+    """Which kernel reduces the bins (host logic, no launch): a wavefront per
+    bin for many few-kilobyte bins, a workgroup per bin for 500-1,999 long
+    bins (eight-byte types from 250), chunks otherwise; the forced modes fall
+    back where their grid would exceed 2^31 threads."""
+    import torch
+    from paper_2307_05389_amd import _lib
+    from paper_2307_05389_amd.api import set_tuning
+    sc = lambda *a, **k: _lib.scan_config(*a, **k)[2]
+    n = 1 << 28                                                          # 1 GB of f32
+    assert sc(torch.float32, n, 1000).startswith("tsds::k_bins_block<")      # 1 MB bins
+    assert sc(torch.float32, n, 100000).startswith("tsds::k_bins_direct<")   # 10 KB bins
+    assert not sc(torch.float32, n, 250).startswith("tsds::k_bins")         # 4 MB bins: chunks
+    assert sc(torch.float64, n // 2, 250).startswith("tsds::k_bins_block<")
+    assert not sc(torch.float32, n, 1000, x_dtype=torch.int64).startswith("tsds::k_bins")  # with x: chunks
+    try:
+        set_tuning(direct=2)
+        assert sc(torch.float32, n, 1 << 23).startswith("tsds::k_bins_block<")
+        assert sc(torch.float32, n, (1 << 23) + 1).startswith("tsds::k_bins_direct<")
+        assert not sc(torch.float32, 1 << 30, (1 << 25) + 1).startswith("tsds::k_bins")
+        with pytest.raises(Exception):
+            set_tuning(direct=3)
+    finally:
+        set_tuning()
