@@ -1,10 +1,15 @@
 // select.hip -- per-bin selection and compaction after the argmin/argmax
 // scan (scan.hip):
 //
-//   k_merge     one wavefront per bin: lexicographic merge of the partials of
-//               a straddling bin, then the bin's sorted distinct selection.
-//   k_compact   one workgroup: exclusive scan of the per-bin counts and the
-//               compaction into strictly increasing indices.
+//   k_merge         one wavefront per bin: lexicographic merge of the partials
+//                   of a straddling bin, then the bin's sorted distinct
+//                   selection (k_merge_lanes: one bin per thread).
+//   k_bins_direct   one wavefront reduces a whole bin and writes its selection
+//                   (replaces the chunked scan and the merge).
+//   k_bins_block    the same with a workgroup of four wavefronts per bin.
+//   k_compact       one workgroup: exclusive scan of the per-bin counts and
+//                   the compaction into strictly increasing indices (many
+//                   workgroups above kCompactSingleMax bins).
 #include <limits>
 #include <type_traits>
 
